@@ -1,0 +1,134 @@
+/*
+ * bfc.h -- butterfly counting in bipartite graphs on AMD Instinct MI355X
+ * (gfx950).  C ABI of libbfc.so.
+ *
+ * Problem (Sec. 2 of Sanei-Mehri, Sariyuce, Tirthapura, "Butterfly Counting
+ * in Bipartite Networks"): G = (L u R, E) is a simple bipartite graph.  A
+ * butterfly is a 2x2 biclique {a,b} x {x,y}; B(G) is their number, B_v the
+ * number containing vertex v, B_e the number containing edge e.
+ *
+ * Conventions for every call below.
+ *  - Vertex ids are uint32, dense per side: 0 <= l < n_left, 0 <= r < n_right.
+ *  - Every pointer named d_* is DEVICE memory owned by the caller (allocate it
+ *    with hipMalloc, torch, ...).  The library never allocates device memory:
+ *    scratch space is a caller workspace whose size a *_ws_size query gives.
+ *    Workspaces and outputs must be 256-byte aligned.
+ *  - Calls run asynchronously on the given stream unless stated otherwise; the
+ *    caller synchronises before reading outputs.  Concurrent calls that share
+ *    a workspace race.
+ *  - Every call returns BFC_OK (0) or a negative BFC_E_* code and never throws
+ *    across the ABI.  bfc_status_str() names a code; after BFC_E_HIP,
+ *    bfc_last_hip_error() gives the HIP error string of the calling thread.
+ *  - Integer counts are exact uint64.  Floating-point estimates are IEEE
+ *    binary64 computed in a fixed order, so they are reproducible bit for bit.
+ */
+#ifndef BFC_H
+#define BFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BFC_OK 0
+#define BFC_E_NULL (-1)          /* a required pointer is NULL */
+#define BFC_E_ARG (-2)           /* bad scalar argument (side, p, N, k, ...) */
+#define BFC_E_ID_RANGE (-3)      /* an edge endpoint id >= its side's size */
+#define BFC_E_DUP_EDGE (-4)      /* the edge list repeats an edge (not simple) */
+#define BFC_E_TOO_LARGE (-5)     /* m >= 2^32 - 64 or a side >= 2^32 - 64 */
+#define BFC_E_WS_SMALL (-6)      /* workspace or storage smaller than queried */
+#define BFC_E_PROBS (-7)         /* probabilities negative, NaN, inf or all 0 */
+#define BFC_E_OVERFLOW_RISK (-8) /* a uint64 count could overflow */
+#define BFC_E_HIP (-9)           /* a HIP runtime call failed */
+#define BFC_E_ALIGN (-10)        /* a device pointer is not 256-byte aligned */
+
+#define BFC_SIDE_AUTO 0          /* the paper's rule (ExactBFC side choice) */
+#define BFC_SIDE_L 1             /* start from L (midpoints in R) */
+#define BFC_SIDE_R 2             /* start from R (midpoints in L) */
+
+const char *bfc_status_str(int code);
+const char *bfc_last_hip_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Graph: both adjacency structures (CSR) of G, built on the device.       */
+/*                                                                          */
+/* Each side's vertices are ranked by (degree ascending, id ascending); rows */
+/* are stored in rank order and every adjacency list holds the ranks of the */
+/* opposite side in ascending order.  The rank is the order "w precedes v"  */
+/* of ExactBFC (Sec. 4): any strict total order counts every same-side pair */
+/* once, and this one keeps the per-start work small.                       */
+/*   off_x[i]..off_x[i+1]  row of the vertex of rank i on side x            */
+/*   adj_x[k]              rank (opposite side) of the k-th neighbour        */
+/*   eid_x[k]              index in the caller's edge list of that edge      */
+/*   xpos_x[k]             position of the same edge in the other side's adj */
+/*   rank_x[id], id_x[rank] the permutation between ids and ranks            */
+/* All arrays live inside one caller-owned storage buffer.                   */
+/* ---------------------------------------------------------------------- */
+typedef struct bfc_graph {
+    uint32_t n_left, n_right;
+    uint64_t n_edges;
+    const uint32_t *off_l, *adj_l, *eid_l, *xpos_l, *rank_l, *id_l;
+    const uint32_t *off_r, *adj_r, *eid_r, *xpos_r, *rank_r, *id_r;
+    /* statistics, host values filled by bfc_graph_build */
+    uint64_t sumsq_l, sumsq_r;            /* sum of squared degrees per side */
+    uint64_t wedges_mid_l, wedges_mid_r;  /* sum of C(d,2): wedges with that midpoint side */
+    uint32_t max_deg_l, max_deg_r;
+    int device;                           /* HIP device the arrays live on */
+} bfc_graph;
+
+/* Bytes of the storage buffer a graph of this size needs. */
+int bfc_graph_storage_size(uint32_t n_left, uint32_t n_right, uint64_t n_edges, size_t *bytes);
+/* Bytes of workspace bfc_graph_build needs (freed by the caller after). */
+int bfc_graph_build_ws_size(uint32_t n_left, uint32_t n_right, uint64_t n_edges, size_t *bytes);
+
+/* Build both CSRs from the caller's edge list d_l[i], d_r[i] (i < n_edges,
+ * device uint32).  Validates the simple-graph assumption of Sec. 2:
+ * BFC_E_ID_RANGE if an id is out of range, BFC_E_DUP_EDGE if an edge repeats.
+ * SYNCHRONOUS: waits for the stream (it reads the statistics back).  The
+ * graph stays valid while the storage buffer lives; the edge list and the
+ * workspace may be freed after the call. */
+int bfc_graph_build(uint32_t n_left, uint32_t n_right, uint64_t n_edges,
+                    const uint32_t *d_l, const uint32_t *d_r,
+                    void *d_storage, size_t storage_bytes,
+                    void *d_ws, size_t ws_bytes, hipStream_t stream, bfc_graph *out);
+
+/* ---------------------------------------------------------------------- */
+/* Exact count, ExactBFC (Sec. 4, Lemma 1 Eq. (3)/(4), Lemma 2).            */
+/* Side choice (BFC_SIDE_AUTO): start from R when sum_L d^2 < sum_R d^2,     */
+/* else from L.  For every start u, midpoint v in N(u) and endpoint w in     */
+/* N(v) ranked above u, C_u[w] is incremented and B += C(C_u[w], 2).         */
+/* ---------------------------------------------------------------------- */
+/* Side that `side` resolves to (BFC_SIDE_L or BFC_SIDE_R), or a BFC_E_*. */
+int bfc_side_used(const bfc_graph *g, int side);
+/* Wedges the count visits from that side: sum over midpoints of C(d,2). */
+int bfc_wedges(const bfc_graph *g, int side, uint64_t *wedges);
+int bfc_exact_ws_size(const bfc_graph *g, int side, size_t *bytes);
+/* Writes B(G) to *d_total (device uint64).  BFC_E_OVERFLOW_RISK if
+ * wedges * (max start degree - 1) / 2 could exceed 2^64 - 1. */
+int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total,
+              void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Local counts (Sec. 2 definitions; Eq. (2); vBFC and eBFC of Sec. 4.2).   */
+/*   B_v = sum over same-side w != v of C(|N(v) & N(w)|, 2)                 */
+/*   B_(a,x) = sum over b in N(x), b != a of (|N(a) & N(b)| - 1)             */
+/* Computed for every vertex / edge in one pass from the cheaper side.      */
+/* Outputs are indexed by the caller's ids (d_cnt_l[n_left], d_cnt_r[n_right]) */
+/* and edge order (d_cnt_e[n_edges]).  Any of the three may be NULL (not    */
+/* wanted), but not all.                                                    */
+/* ---------------------------------------------------------------------- */
+int bfc_local_ws_size(const bfc_graph *g, size_t *bytes);
+int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t *d_cnt_e,
+              void *d_ws, size_t ws_bytes, hipStream_t stream);
+int bfc_per_vertex(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r,
+                   void *d_ws, size_t ws_bytes, hipStream_t stream);
+int bfc_per_edge(const bfc_graph *g, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes,
+                 hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFC_H */

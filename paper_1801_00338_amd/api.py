@@ -1,0 +1,140 @@
+"""Python front end of the HIP library.
+
+PyTorch supplies device memory (tensors) and streams; the library does every
+step of the computation.  Device buffers are kept alive by the objects that
+hand their pointers to the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BFC_SIDE_AUTO, BFC_SIDE_L, BFC_SIDE_R, check, lib  # noqa: F401
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _bytes(n, device):
+    return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
+
+
+def to_device_u32(a, device="cuda"):
+    """numpy/torch uint32 ids -> contiguous device tensor (int32 storage)."""
+    if isinstance(a, torch.Tensor):
+        t = a
+        if t.dtype == torch.uint32:
+            t = t.view(torch.int32)
+        elif t.dtype != torch.int32:
+            t = t.to(torch.int32)
+        return t.to(device).contiguous()
+    arr = np.ascontiguousarray(a, dtype=np.uint32)
+    return torch.from_numpy(arr.view(np.int32)).to(device)
+
+
+class Graph:
+    """A bipartite graph resident in device memory (both CSRs, rank order)."""
+
+    def __init__(self, n_left, n_right, l, r, device="cuda", stream=None):
+        L = lib()
+        self.device = torch.device(device)
+        dl = to_device_u32(l, self.device)
+        dr = to_device_u32(r, self.device)
+        if dl.numel() != dr.numel():
+            raise ValueError("l and r differ in length")
+        m = dl.numel()
+        sz = C.c_size_t()
+        check(L.bfc_graph_storage_size(n_left, n_right, m, C.byref(sz)), "storage size")
+        self.storage = _bytes(sz.value, self.device)
+        check(L.bfc_graph_build_ws_size(n_left, n_right, m, C.byref(sz)), "build ws size")
+        ws = _bytes(sz.value, self.device)
+        self.g = _lib.bfc_graph()
+        check(L.bfc_graph_build(n_left, n_right, m, C.c_void_p(dl.data_ptr()),
+                                C.c_void_p(dr.data_ptr()), C.c_void_p(self.storage.data_ptr()),
+                                self.storage.numel(), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream(stream), C.byref(self.g)), "graph build")
+        del ws
+        self.n_left, self.n_right, self.n_edges = n_left, n_right, m
+        self._ws = None
+
+    # -------------------------------------------------------------- stats
+    @property
+    def sumsq(self):
+        return self.g.sumsq_l, self.g.sumsq_r
+
+    @property
+    def max_degree(self):
+        return self.g.max_deg_l, self.g.max_deg_r
+
+    def side_used(self, side=BFC_SIDE_AUTO):
+        rc = lib().bfc_side_used(C.byref(self.g), side)
+        if rc < 0:
+            check(rc, "side")
+        return rc
+
+    def wedges(self, side=BFC_SIDE_AUTO):
+        w = C.c_uint64()
+        check(lib().bfc_wedges(C.byref(self.g), side, C.byref(w)), "wedges")
+        return w.value
+
+    def workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = _bytes(nbytes, self.device)
+        return self._ws
+
+    # -------------------------------------------------------------- exact
+    def exact_ws_size(self, side=BFC_SIDE_AUTO):
+        sz = C.c_size_t()
+        check(lib().bfc_exact_ws_size(C.byref(self.g), side, C.byref(sz)), "exact ws size")
+        return sz.value
+
+    def exact_async(self, out, side=BFC_SIDE_AUTO, stream=None):
+        """Queue the exact count; out is a 1-element int64 device tensor."""
+        ws = self.workspace(self.exact_ws_size(side))
+        check(lib().bfc_exact(C.byref(self.g), side, C.c_void_p(out.data_ptr()),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "exact")
+        return out
+
+    def exact(self, side=BFC_SIDE_AUTO):
+        out = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.exact_async(out, side)
+        torch.cuda.synchronize(self.device)
+        return int(out.cpu().numpy().view(np.uint64)[0])
+
+    # -------------------------------------------------------------- local
+    def local_ws_size(self):
+        sz = C.c_size_t()
+        check(lib().bfc_local_ws_size(C.byref(self.g), C.byref(sz)), "local ws size")
+        return sz.value
+
+    def local_async(self, cnt_l=None, cnt_r=None, cnt_e=None, stream=None):
+        ws = self.workspace(self.local_ws_size())
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        check(lib().bfc_local(C.byref(self.g), ptr(cnt_l), ptr(cnt_r), ptr(cnt_e),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "local")
+
+    def local(self, vertices=True, edges=True):
+        d = self.device
+        cl = torch.zeros(max(self.n_left, 1), dtype=torch.int64, device=d) if vertices else None
+        cr = torch.zeros(max(self.n_right, 1), dtype=torch.int64, device=d) if vertices else None
+        ce = torch.zeros(max(self.n_edges, 1), dtype=torch.int64, device=d) if edges else None
+        self.local_async(cl, cr, ce)
+        torch.cuda.synchronize(d)
+        u = lambda t, n: t.cpu().numpy().view(np.uint64)[:n].copy() if t is not None else None
+        return u(cl, self.n_left), u(cr, self.n_right), u(ce, self.n_edges)
+
+    def per_vertex(self):
+        cl, cr, _ = self.local(vertices=True, edges=False)
+        return cl, cr
+
+    def per_edge(self):
+        return self.local(vertices=False, edges=True)[2]
+
+
+def exact(n_left, n_right, l, r, side=BFC_SIDE_AUTO):
+    return Graph(n_left, n_right, l, r).exact(side)

@@ -1,0 +1,155 @@
+// Internal helpers shared by the library's HIP sources (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/bfc.h"
+
+namespace bfc {
+
+// ------------------------------------------------------------------ errors
+void set_hip_error(hipError_t e);
+
+#define BFC_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) {                         \
+            ::bfc::set_hip_error(e_);                   \
+            return BFC_E_HIP;                           \
+        }                                               \
+    } while (0)
+
+#define BFC_TRY(call)                                   \
+    do {                                                \
+        int rc_ = (call);                               \
+        if (rc_ != BFC_OK) return rc_;                  \
+    } while (0)
+
+// ------------------------------------------------------------------ workspace carving
+// Hands out 256-byte aligned sub-buffers of a caller buffer.  With base ==
+// nullptr it only counts bytes (for the *_ws_size queries).
+struct Carver {
+    char *base;
+    size_t cap;
+    size_t used = 0;
+    Carver(void *b, size_t c) : base((char *)b), cap(c) {}
+    template <class T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        if (bytes == 0) bytes = 256;
+        T *p = base ? (T *)(base + used) : nullptr;
+        used += bytes;
+        return p;
+    }
+    bool fits() const { return base == nullptr || used <= cap; }
+};
+
+inline bool aligned256(const void *p) { return ((uintptr_t)p & 255) == 0; }
+
+// Arrays are padded to a multiple of 64 elements so that 16-byte vector
+// loads of aligned groups never run past an allocation.
+inline size_t pad64(uint64_t n) { return (size_t)((n + 64) & ~uint64_t(63)); }
+
+int device_cu_count(int device);
+
+// ------------------------------------------------------------------ scans
+// Inclusive prefix sum of n uint32 values (may alias in/out).  tmp must hold
+// scan_tmp_elems(n) uint32.  Sums must fit in uint32.
+size_t scan_tmp_elems(uint64_t n);
+int scan_u32_inclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp,
+                       hipStream_t s);
+
+// ------------------------------------------------------------------ device helpers
+constexpr int WAVE = 64;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ inline uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v = min(v, (uint32_t)__shfl_xor(v, d, WAVE));
+    return v;
+}
+
+__device__ inline unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// Block-wide exclusive scan of one uint32 per thread (NT threads, NT/64
+// waves).  `red` is __shared__ scratch of NT/64 + 1 words.  Returns the
+// exclusive prefix; *total receives the block sum.  Contains barriers.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == WAVE - 1) red[wid] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / WAVE; w++) {
+        uint32_t x = red[w];
+        if (w < wid) base += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+template <int NT>
+__device__ inline uint32_t block_min(uint32_t v, uint32_t *red) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    v = wave_min(v);
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    uint32_t m = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / WAVE; w++) m = min(m, red[w]);
+    __syncthreads();
+    return m;
+}
+
+template <int NT>
+__device__ inline unsigned long long block_sum64(unsigned long long v,
+                                                 unsigned long long *red) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    v = wave_sum64(v);
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+#pragma unroll
+    for (int w = 0; w < NT / WAVE; w++) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// First index j in [0, n) with a[j] > x (a non-decreasing), in LDS.
+__device__ inline uint32_t upper_bound_lds(const uint32_t *a, uint32_t n, uint32_t x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] > x) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// First position p in [lo, hi) with a[p] >= x (a ascending), global memory.
+__device__ inline uint32_t lower_bound_glb(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace bfc

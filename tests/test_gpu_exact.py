@@ -1,0 +1,136 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Every call goes through the C ABI (paper_1801_00338_amd.api -> libbfc.so).
+Exact counts are integers and must match bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_00338_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1801_00338_amd import api as a
+    a.lib()
+    oracle.build(force=False)
+    return a
+
+
+def rand_graph(rng, nl, nr, m):
+    m = min(m, nl * nr)
+    keys = rng.choice(nl * nr, size=m, replace=False)
+    return (keys // nr).astype(np.uint32), (keys % nr).astype(np.uint32)
+
+
+def check_all(api, nl, nr, l, r, local=True, sides=(0, 1, 2)):
+    print(f"case nl={nl} nr={nr} m={l.size}", flush=True)
+    g = api.Graph(nl, nr, l, r)
+    want = oracle.exact(nl, nr, l, r)[0]
+    for side in sides:
+        got = g.exact(side)
+        assert got == want, (side, got, want)
+    sl, sr, ml, mr = oracle.degree_stats(nl, nr, l, r)
+    assert g.sumsq == (sl, sr)
+    assert g.max_degree == (ml, mr)
+    if local:
+        cl, cr, ce = g.local()
+        ol, orr = oracle.per_vertex(nl, nr, l, r)
+        oe = oracle.per_edge(nl, nr, l, r)
+        assert np.array_equal(cl, ol)
+        assert np.array_equal(cr, orr)
+        assert np.array_equal(ce, oe)
+    return want
+
+
+def test_tiny_random_graphs(api):
+    rng = np.random.default_rng(100)
+    for _ in range(60):
+        nl, nr = rng.integers(1, 30, size=2)
+        l, r = rand_graph(rng, nl, nr, rng.integers(0, nl * nr + 1))
+        check_all(api, int(nl), int(nr), l, r)
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 2), (2, 3), (17, 5), (300, 3), (3, 300), (64, 64)])
+def test_complete_bipartite(api, a, b):
+    l, r = gen.biclique(a, b)
+    B = check_all(api, a, b, l, r)
+    assert B == (a * (a - 1) // 2) * (b * (b - 1) // 2)
+
+
+def test_dataset_table_biclique(api):
+    # first row of the paper's dataset table: (10^4, 10)-biclique
+    l, r = gen.biclique(10_000, 10)
+    g = api.Graph(10_000, 10, l, r)
+    assert g.exact() == 2_249_775_000
+    assert g.sumsq == (1_000_000, 1_000_000_000)
+    assert g.side_used() == 2
+    cl, cr, ce = g.local()
+    assert (cl == 9_999 * 45).all() and (cr == 9 * (10_000 * 9_999 // 2)).all()
+    assert (ce == 9_999 * 9).all()
+
+
+def test_empty_and_isolated(api):
+    e = np.zeros(0, np.uint32)
+    g = api.Graph(5, 7, e, e)
+    assert g.exact() == 0
+    cl, cr, ce = g.local()
+    assert cl.tolist() == [0] * 5 and cr.tolist() == [0] * 7 and ce.size == 0
+    # a single edge among many isolated vertices
+    g = api.Graph(1000, 1000, np.array([999], np.uint32), np.array([0], np.uint32))
+    assert g.exact() == 0
+
+
+def test_errors(api):
+    from paper_1801_00338_amd._lib import BfcError
+    with pytest.raises(BfcError, match="DUP"):
+        api.Graph(2, 2, np.array([0, 0], np.uint32), np.array([1, 1], np.uint32))
+    with pytest.raises(BfcError, match="ID_RANGE"):
+        api.Graph(2, 2, np.array([0, 2], np.uint32), np.array([1, 1], np.uint32))
+    g = api.Graph(2, 2, np.array([0], np.uint32), np.array([1], np.uint32))
+    with pytest.raises(BfcError, match="ARG"):
+        g.exact(side=7)
+
+
+def test_er_2k_3k_20k(api):
+    w = gen.WORKLOADS["er_2k_3k_20k"]
+    l, r = w.edges()
+    check_all(api, w.nl, w.nr, l, r)
+
+
+def test_chung_lu_small_hubs(api):
+    # power-law graph with hub starts (degree >= 256 takes the wide path)
+    nl, nr = 3000, 15000
+    l, r = gen.chung_lu(nl, nr, 150_000, 2.1, 2.3, 2000, seed=7)
+    check_all(api, nl, nr, l, r)
+
+
+def test_many_windows(api):
+    # more than two 2^16-rank windows on either side, sparse: exercises the
+    # window walk, skipped windows and the segment boundaries
+    nl, nr = 200_000, 150_000
+    l, r = gen.chung_lu(nl, nr, 600_000, 2.2, 2.4, 5000, seed=11)
+    check_all(api, nl, nr, l, r, local=False)
+    g = api.Graph(nl, nr, l, r)
+    cl, cr, ce = g.local()
+    ol, orr = oracle.per_vertex(nl, nr, l, r)
+    assert np.array_equal(cl, ol) and np.array_equal(cr, orr)
+    assert np.array_equal(ce, oracle.per_edge(nl, nr, l, r))
+
+
+def test_dense_windows_multi_round(api):
+    # Starting from L (forced, side 1): 4000 starts of degree 50 whose
+    # midpoints have ~2000 entries each, so one window holds far more 4-entry
+    # groups than the workgroup has lanes (the full table clear path).  The
+    # automatic side starts from R: 100 starts of degree ~2000 (wide path).
+    rng = np.random.default_rng(5)
+    nl, nr = 4000, 100
+    l = np.repeat(np.arange(nl, dtype=np.uint32), 50)
+    r = np.concatenate([rng.choice(nr, 50, replace=False) for _ in range(nl)]).astype(np.uint32)
+    check_all(api, nl, nr, l, r)
