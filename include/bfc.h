@@ -107,9 +107,19 @@ int bfc_side_used(const bfc_graph *g, int side);
 int bfc_wedges(const bfc_graph *g, int side, uint64_t *wedges);
 int bfc_exact_ws_size(const bfc_graph *g, int side, size_t *bytes);
 /* Writes B(G) to *d_total (device uint64).  BFC_E_OVERFLOW_RISK if
- * wedges * (max start degree - 1) / 2 could exceed 2^64 - 1. */
+ * wedges * (max start degree - 1) / 2 could exceed 2^64 - 1.
+ * bfc_exact = bfc_exact_plan + bfc_exact_count. */
 int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total,
               void *d_ws, size_t ws_bytes, hipStream_t stream);
+/* The two halves of bfc_exact.  The plan (per-call preparation of ExactBFC's
+ * walk: adjacency segments at counter-window boundaries, per-start wedge
+ * counts and the largest-first work queue) is written into the workspace;
+ * bfc_exact_count launches the count itself and may be repeated on a
+ * workspace planned for the same graph and side. */
+int bfc_exact_plan(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes,
+                   hipStream_t stream);
+int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total,
+                    void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------- */
 /* Local counts (Sec. 2 definitions; Eq. (2); vBFC and eBFC of Sec. 4.2).   */

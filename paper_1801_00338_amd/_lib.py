@@ -61,6 +61,10 @@ SIGNATURES = {
     "bfc_exact_ws_size": ([C.POINTER(bfc_graph), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "bfc_exact": ([C.POINTER(bfc_graph), C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
                    C.c_void_p], C.c_int),
+    "bfc_exact_plan": ([C.POINTER(bfc_graph), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p],
+                       C.c_int),
+    "bfc_exact_count": ([C.POINTER(bfc_graph), C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
+                         C.c_void_p], C.c_int),
     "bfc_local_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
     "bfc_local": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                    C.c_size_t, C.c_void_p], C.c_int),

@@ -100,6 +100,19 @@ class Graph:
                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "exact")
         return out
 
+    def exact_plan(self, side=BFC_SIDE_AUTO, stream=None):
+        ws = self.workspace(self.exact_ws_size(side))
+        check(lib().bfc_exact_plan(C.byref(self.g), side, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream(stream)), "exact plan")
+
+    def exact_count(self, out, side=BFC_SIDE_AUTO, stream=None):
+        """Queue the count on a workspace planned by exact_plan for this side."""
+        ws = self.workspace(self.exact_ws_size(side))
+        check(lib().bfc_exact_count(C.byref(self.g), side, C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+              "exact count")
+        return out
+
     def exact(self, side=BFC_SIDE_AUTO):
         out = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.exact_async(out, side)

@@ -134,8 +134,30 @@ struct QueueState {
     uint32_t bcount[NBUCKET];
     uint32_t cursor[NBUCKET];
     uint32_t n_items;
-    uint32_t head;
+    uint32_t head;                      // next item to hand out
+    uint32_t done;                      // workgroups finished
+    uint32_t pad;
+    unsigned long long acc;             // running total of the launch
 };
+
+// End of a persistent launch: add this workgroup's sum; the last workgroup
+// to finish publishes the total and re-arms the queue for the next launch.
+__device__ inline void finish_launch(QueueState *q, unsigned long long part,
+                                     unsigned long long *total) {
+    if (threadIdx.x != 0) return;
+    if (part) atomicAdd(&q->acc, part);
+    __threadfence();
+    uint32_t d = atomicAdd(&q->done, 1u);
+    if (d == gridDim.x - 1) {
+        __threadfence();
+        unsigned long long t = atomicAdd(&q->acc, 0ull);
+        if (total) *total = t;
+        q->acc = 0;
+        q->head = 0;
+        q->done = 0;
+        __threadfence();
+    }
+}
 
 __global__ void k_bucket_offsets(QueueState *q, unsigned long long *total) {
     if (threadIdx.x == 0) {
@@ -371,7 +393,7 @@ __global__ __launch_bounds__(NT) void k_exact(CountArgs a) {
         else acc += count_wide(a, sh, u, rb, du);
     }
     acc = block_sum64<NT>(acc, sh.red64);
-    if (threadIdx.x == 0 && acc) atomicAdd(a.total, acc);
+    finish_launch(a.q, acc, a.total);
 }
 
 // ------------------------------------------------------------------ local counts
@@ -627,6 +649,7 @@ __global__ __launch_bounds__(NT) void k_local(LocalArgs a) {
         if (du < (uint32_t)NT) local_narrow(a, ls, u, rb, du);
         else local_wide(a, ls, u, rb, du);
     }
+    finish_launch(a.c.q, 0, nullptr);
 }
 
 // B_v of the midpoint side from the edge sums; outputs in caller ids.
@@ -732,19 +755,38 @@ int bfc_exact_ws_size(const bfc_graph *g, int side, size_t *bytes) {
     return BFC_OK;
 }
 
-int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws, size_t ws_bytes,
-              hipStream_t s) {
-    if (!d_total || !d_ws) return BFC_E_NULL;
-    Plan p;
+static int exact_setup(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes, Plan &p,
+                       ExactWs &w) {
+    if (!d_ws) return BFC_E_NULL;
     BFC_TRY(make_plan(g, side, &p));
-    if (!aligned256(d_ws) || ((uintptr_t)d_total & 7)) return BFC_E_ALIGN;
+    if (!aligned256(d_ws)) return BFC_E_ALIGN;
     if (overflow_risk(p)) return BFC_E_OVERFLOW_RISK;
     Carver c(d_ws, ws_bytes);
-    ExactWs w = carve_exact(c, p);
+    w = carve_exact(c, p);
     if (!c.fits()) return BFC_E_WS_SMALL;
+    return BFC_OK;
+}
+
+int bfc_exact_plan(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    Plan p;
+    ExactWs w;
+    BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
+    return prepare(p, w, nullptr, 0, s);
+}
+
+int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws,
+                    size_t ws_bytes, hipStream_t s) {
+    if (!d_total) return BFC_E_NULL;
+    if ((uintptr_t)d_total & 7) return BFC_E_ALIGN;
+    Plan p;
+    ExactWs w;
+    BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
     unsigned long long *tot = (unsigned long long *)d_total;
-    BFC_TRY(prepare(p, w, tot, 0, s));
-    if (p.nA == 0 || p.m == 0) return BFC_OK;
+    if (p.nA == 0 || p.m == 0) {
+        k_zero_u64<<<1, 64, 0, s>>>(tot, 1);
+        BFC_HIP(hipGetLastError());
+        return BFC_OK;
+    }
     CountArgs a;
     a.offA = p.offA; a.adjA = p.adjA; a.xA = p.xA; a.offB = p.offB; a.adjB = p.adjB;
     a.seg1 = w.seg1; a.seg_start = w.seg_start; a.seg_win = w.seg_win;
@@ -755,6 +797,13 @@ int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws, size_
     k_exact<<<grid, NT, 0, s>>>(a);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
+}
+
+int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws, size_t ws_bytes,
+              hipStream_t s) {
+    if (!d_total) return BFC_E_NULL;
+    BFC_TRY(bfc_exact_plan(g, side, d_ws, ws_bytes, s));
+    return bfc_exact_count(g, side, d_total, d_ws, ws_bytes, s);
 }
 
 }  // extern "C"

@@ -8,31 +8,63 @@ Two families stand in for the KONECT graphs of the paper's dataset table
 (Sec. 2, "Networks and Experimental Setup"): uniform (Erdos-Renyi style)
 bipartite graphs and Chung-Lu power-law bipartite graphs.  The paper removes
 multi-edges and self loops; bipartite graphs have no self loops, and both
-generators drop duplicate (l, r) pairs.
+generators drop repeated (l, r) pairs.
 
-Recipe (fixed, deterministic for a given seed, numpy PCG64 stream):
+Recipe (deterministic for a given seed; the sampler is gen_native.c, a
+SplitMix64 stream with Walker alias tables):
 
-* ER(nl, nr, m, seed): endpoints drawn uniformly and independently on each
+* er(nl, nr, m, seed): endpoints drawn uniformly and independently on each
   side; the first m distinct pairs in draw order are kept.
-* Chung-Lu(nl, nr, m, gamma_l, gamma_r, cap, seed): vertex i of a side of size
+* chung_lu(nl, nr, m, gamma_l, gamma_r, cap, seed): vertex i of a side of size
   n gets weight (i+1)^(-1/(gamma-1)); expected degrees m*w_i/sum(w) are capped
   at ``cap`` by iterated capping (the excess is redistributed proportionally
-  over the uncapped vertices until no vertex exceeds the cap); endpoints are
-  then drawn independently on each side with probability proportional to the
-  capped expected degree, and the first m distinct pairs in draw order are
-  kept.  Finally each side's ids are relabelled by a seeded random permutation
-  so that hubs are not clustered at low ids.
+  over the uncapped vertices until none exceeds the cap); endpoints are drawn
+  independently on each side with probability proportional to the capped
+  expected degree, the first m distinct pairs in draw order are kept, and each
+  side's ids are relabelled by a seeded random permutation so that hubs are
+  not clustered at low ids.
 
 Edges come back in draw order (not sorted), as uint32 numpy arrays.
 """
 from __future__ import annotations
 
+import ctypes as C
 import math
+import os
+import subprocess
 
 import numpy as np
 
 __all__ = ["er", "chung_lu", "capped_expected_degrees", "biclique",
-           "disjoint_union", "Workload", "WORKLOADS", "make_workload"]
+           "disjoint_union", "Workload", "WORKLOADS", "make_workload", "build_native"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen_native.c")
+_LIB = os.path.join(_HERE, "libbfcgen.so")
+_lib = None
+
+
+def build_native(force: bool = True) -> str:
+    """Compile the sampler with gcc (host code only)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _native():
+    global _lib
+    if _lib is None:
+        build_native(force=False)
+        L = C.CDLL(_LIB)
+        u32p = C.POINTER(C.c_uint32)
+        dp = C.POINTER(C.c_double)
+        L.gen_er.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, u32p, u32p]
+        L.gen_weighted.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, dp, dp, C.c_uint64,
+                                   C.c_int, u32p, u32p]
+        _lib = L
+    return _lib
 
 
 def capped_expected_degrees(n: int, m: int, gamma: float, cap: float) -> np.ndarray:
@@ -57,70 +89,44 @@ def capped_expected_degrees(n: int, m: int, gamma: float, cap: float) -> np.ndar
     return e
 
 
-def _first_distinct(rng, m: int, draw, nr: int) -> tuple[np.ndarray, np.ndarray]:
-    """Draw (l, r) batches from ``draw`` until m distinct pairs exist; keep the
-    first m distinct ones in draw order."""
-    keys = np.zeros(0, dtype=np.uint64)
-    have = 0
-    batches = []
-    while True:
-        need = m - have
-        size = int(need * 1.15) + 4096
-        l, r = draw(size)
-        batches.append(l.astype(np.uint64) * np.uint64(nr) + r.astype(np.uint64))
-        keys = np.concatenate(batches) if len(batches) > 1 else batches[0]
-        batches = [keys]
-        _, first = np.unique(keys, return_index=True)
-        have = first.size
-        if have >= m:
-            first.sort()
-            sel = keys[first[:m]]
-            l_out = (sel // np.uint64(nr)).astype(np.uint32)
-            r_out = (sel % np.uint64(nr)).astype(np.uint32)
-            return l_out, r_out
-        if len(keys) > 64 * max(m, 1) + 10**6:
-            raise ValueError("graph too dense for the requested edge count")
+def _u32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint32))
+
+
+def _check(rc):
+    if rc == -2:
+        raise ValueError("graph too dense: could not draw enough distinct edges")
+    if rc == -3:
+        raise ValueError("m exceeds |L|*|R|")
+    if rc != 0:
+        raise MemoryError("generator out of memory")
 
 
 def er(nl: int, nr: int, m: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     """Uniform bipartite graph with exactly m distinct edges."""
     if m > nl * nr:
         raise ValueError("m exceeds |L|*|R|")
-    if m == 0:
-        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
-    rng = np.random.Generator(np.random.PCG64(seed))
-
-    def draw(size):
-        return (rng.integers(0, nl, size, dtype=np.int64),
-                rng.integers(0, nr, size, dtype=np.int64))
-
-    return _first_distinct(rng, m, draw, nr)
+    l = np.zeros(max(m, 1), np.uint32)
+    r = np.zeros(max(m, 1), np.uint32)
+    if m:
+        _check(_native().gen_er(nl, nr, m, seed, _u32p(l), _u32p(r)))
+    return l[:m], r[:m]
 
 
 def chung_lu(nl: int, nr: int, m: int, gamma_l: float, gamma_r: float,
              cap: float, seed: int) -> tuple[np.ndarray, np.ndarray]:
     """Chung-Lu power-law bipartite graph with exactly m distinct edges."""
-    if m == 0:
-        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
-    cap_l = min(cap, nr)
-    cap_r = min(cap, nl)
-    el = capped_expected_degrees(nl, m, gamma_l, cap_l)
-    er_ = capped_expected_degrees(nr, m, gamma_r, cap_r)
-    cl = np.cumsum(el)
-    cr = np.cumsum(er_)
-    rng = np.random.Generator(np.random.PCG64(seed))
-
-    def draw(size):
-        ul = rng.random(size) * cl[-1]
-        ur = rng.random(size) * cr[-1]
-        li = np.minimum(np.searchsorted(cl, ul, side="right"), nl - 1)
-        ri = np.minimum(np.searchsorted(cr, ur, side="right"), nr - 1)
-        return li, ri
-
-    l, r = _first_distinct(rng, m, draw, nr)
-    perm_l = rng.permutation(nl).astype(np.uint32)
-    perm_r = rng.permutation(nr).astype(np.uint32)
-    return perm_l[l], perm_r[r]
+    if m > nl * nr:
+        raise ValueError("m exceeds |L|*|R|")
+    l = np.zeros(max(m, 1), np.uint32)
+    r = np.zeros(max(m, 1), np.uint32)
+    if m:
+        el = np.ascontiguousarray(capped_expected_degrees(nl, m, gamma_l, min(cap, nr)))
+        er_ = np.ascontiguousarray(capped_expected_degrees(nr, m, gamma_r, min(cap, nl)))
+        dp = C.POINTER(C.c_double)
+        _check(_native().gen_weighted(nl, nr, m, el.ctypes.data_as(dp), er_.ctypes.data_as(dp),
+                                      seed, 1, _u32p(l), _u32p(r)))
+    return l[:m], r[:m]
 
 
 def biclique(a: int, b: int) -> tuple[np.ndarray, np.ndarray]:
