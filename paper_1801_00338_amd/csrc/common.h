@@ -51,6 +51,10 @@ inline bool aligned256(const void *p) { return ((uintptr_t)p & 255) == 0; }
 // loads of aligned groups never run past an allocation.
 inline size_t pad64(uint64_t n) { return (size_t)((n + 64) & ~uint64_t(63)); }
 
+// Entries readable past the end of an adjacency array: the count kernels load
+// whole 16-entry pieces whose tail may run beyond the last list.
+constexpr uint64_t ADJ_SLACK = 64;
+
 int device_cu_count(int device);
 
 // ------------------------------------------------------------------ scans

@@ -1,4 +1,5 @@
-// Exact butterfly count (ExactBFC, Sec. 4 of the paper) on gfx950.
+// Exact and local butterfly counts (ExactBFC, vBFC, eBFC; Sec. 4 of the
+// paper) on gfx950.
 //
 // Work decomposition.  The start side A is chosen by the paper's rule (the
 // side whose opposite has the smaller sum of squared degrees is walked as
@@ -7,35 +8,49 @@
 // lists are sorted by rank, that suffix begins right after u's own position
 // in adj_B[v] (xpos) and no search is needed.
 //
-// Counting table.  C_u[w] lives in LDS as a dense window of the rank space:
-// with d_u <= 255 every count fits a byte (C_u[w] <= d_u), so a 64 KiB table
-// covers 65536 consecutive ranks; wider starts use 32-bit counters over
-// 16384 ranks.  Each wedge adds one with a returning LDS atomic, and the old
-// value is what the pair {u, w} gains (C(c+1,2) - C(c,2) = c), so the fold
-// C(C_u[w], 2) happens as the walk goes.
+// Counting table.  C_u[w] lives in LDS as a dense window of the rank space.
+// Each wedge adds one with a returning LDS atomic and the old value is what
+// the pair {u, w} gains (C(c+1,2) - C(c,2) = c), so the fold C(C_u[w], 2)
+// happens during the walk.
 //
-// Windows.  Each adjacency list of B is cut into segments at window
-// boundaries (a planning pass).  A start walks its midpoints' suffixes one
-// window at a time, in increasing window order, skipping windows no suffix
-// touches: per window every midpoint contributes at most one contiguous
-// sub-run.  Sub-runs are cut into 16-byte aligned groups of 4 entries, the
-// groups of all midpoints are spread over the workgroup's lanes (an LDS
-// prefix sum and binary search map a group to its midpoint), and each lane
-// does one 16-byte load per group.
+// Narrow starts (d_u <= 255).  C_u[w] <= d_u fits a byte.  One wavefront owns
+// one start and a private 16 KiB table = a window of 2^14 ranks, so nothing
+// is shared between waves and a window needs no workgroup barrier.  Every
+// adjacency list of B is cut into segments at window boundaries (planning
+// pass); the wave walks its midpoints' suffixes window by window in
+// increasing order, skipping windows no suffix touches: in a window each
+// midpoint contributes at most one contiguous sub-run.  Sub-runs are cut into
+// pieces of 16 entries (4 aligned 16-byte groups), the pieces of all
+// midpoints are spread over the 64 lanes (a wave prefix sum plus an LDS
+// binary search map a piece to its midpoint) and each lane does four 16-byte
+// loads per piece.
+//
+// Wide starts (d_u > 255, few).  A 512-lane workgroup with a 64 KiB table of
+// 32-bit counters (2^14 ranks), midpoints in batches of 256, sub-runs found by
+// binary search.
 //
 // Scheduling.  Starts are bucketed by their wedge count (log2) and handed out
-// largest first through an atomic queue to a persistent grid.
+// largest first through an atomic queue per class to persistent grids.
 #include "common.h"
 
 namespace bfc {
 
-constexpr int NT = 256;                 // threads per workgroup
-constexpr int TBL_BYTES = 65536;        // LDS counter table
-constexpr int G_SHIFT = 16;             // window = 2^16 ranks (byte counters)
-constexpr int W32_SHIFT = 14;           // 2^14 ranks with 32-bit counters
-constexpr int KEEP = 2;                 // groups per lane kept for the cheap clear
 constexpr uint32_t INF = 0xFFFFFFFFu;
 constexpr int NBUCKET = 66;
+constexpr int G_SHIFT = 14;             // window = 2^14 ranks (segment granularity)
+constexpr uint32_t NARROW_MAX = 255;    // byte counters: C_u[w] <= d_u <= 255
+
+// narrow kernels: one wave per workgroup
+constexpr int WT = 64;
+constexpr int WTBL_BYTES = 1 << G_SHIFT;
+constexpr uint32_t WTBL_WORDS = WTBL_BYTES / 4;
+constexpr int WSLOTS = 4;               // midpoints per lane (4 * 64 > NARROW_MAX)
+constexpr int WCHUNK = 4;               // starts taken from the queue at once
+
+// wide kernels: 512-lane workgroups
+constexpr int NT = 512;
+constexpr int MIDS = 256;
+constexpr int TBL_WORDS = 1 << G_SHIFT; // 32-bit counters, 64 KiB
 
 struct Plan {
     int start_r;                        // 0: starts in L, 1: starts in R
@@ -97,15 +112,25 @@ __global__ void k_seg_fill(const uint32_t *adjB, uint64_t m, const uint32_t *seg
     }
 }
 
+// The two classes of starts each have a largest-first queue.
+struct QueueState {
+    uint32_t bcount[2][NBUCKET];
+    uint32_t cursor[2][NBUCKET];
+    uint32_t n_items[2];
+    uint32_t head[2];                   // next item to hand out
+    uint32_t done[2];                   // workgroups finished
+    unsigned long long acc;             // running total of the count
+};
+
 // Wedges of start u: sum over v in N(u) of the entries of adj_B[v] after u
 // (all entries but u itself when `all_ends`, for the local counts).
-// Bucket = bit length of that count (0 = nothing to do).
+// Bucket = bit length of that count (0 = nothing to do); class 1 = wide.
 __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32_t *adjA,
                                               const uint32_t *xA, const uint32_t *offB,
                                               uint32_t nA, int all_ends, uint8_t *bucket,
-                                              uint32_t *bcount) {
-    __shared__ uint32_t hist[NBUCKET];
-    for (int i = threadIdx.x; i < NBUCKET; i += blockDim.x) hist[i] = 0;
+                                              QueueState *q) {
+    __shared__ uint32_t hist[2][NBUCKET];
+    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const uint32_t wpb = blockDim.x / WAVE;
@@ -119,75 +144,52 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
         t = wave_sum64(t);
         if (lane == 0) {
             uint32_t b = t ? 64 - __clzll(t) : 0;
-            bucket[u] = (uint8_t)b;
-            if (b) atomicAdd(&hist[b], 1u);
+            uint32_t cls = (re - rb) > NARROW_MAX;
+            bucket[u] = (uint8_t)(b | cls << 7);
+            if (b) atomicAdd(&hist[cls][b], 1u);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < NBUCKET; i += blockDim.x)
-        if (hist[i]) atomicAdd(&bcount[i], hist[i]);
+    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x)
+        if ((&hist[0][0])[i]) atomicAdd(&(&q->bcount[0][0])[i], (&hist[0][0])[i]);
 }
 
 // Bucket b's items start after all larger buckets (largest work first).
-// Also zeroes the queue head and the output total.
-struct QueueState {
-    uint32_t bcount[NBUCKET];
-    uint32_t cursor[NBUCKET];
-    uint32_t n_items;
-    uint32_t head;                      // next item to hand out
-    uint32_t done;                      // workgroups finished
-    uint32_t pad;
-    unsigned long long acc;             // running total of the launch
-};
-
-// End of a persistent launch: add this workgroup's sum; the last workgroup
-// to finish publishes the total and re-arms the queue for the next launch.
-__device__ inline void finish_launch(QueueState *q, unsigned long long part,
-                                     unsigned long long *total) {
-    if (threadIdx.x != 0) return;
-    if (part) atomicAdd(&q->acc, part);
-    __threadfence();
-    uint32_t d = atomicAdd(&q->done, 1u);
-    if (d == gridDim.x - 1) {
-        __threadfence();
-        unsigned long long t = atomicAdd(&q->acc, 0ull);
-        if (total) *total = t;
-        q->acc = 0;
-        q->head = 0;
-        q->done = 0;
-        __threadfence();
-    }
-}
-
-__global__ void k_bucket_offsets(QueueState *q, unsigned long long *total) {
-    if (threadIdx.x == 0) {
+__global__ void k_bucket_offsets(QueueState *q) {
+    if (threadIdx.x < 2) {
+        const int c = threadIdx.x;
         uint32_t run = 0;
         for (int b = NBUCKET - 1; b >= 1; b--) {
-            q->cursor[b] = run;
-            run += q->bcount[b];
+            q->cursor[c][b] = run;
+            run += q->bcount[c][b];
         }
-        q->n_items = run;
-        q->head = 0;
-        if (total) *total = 0;
+        q->n_items[c] = run;
+        q->head[c] = 0;
+        q->done[c] = 0;
     }
+    if (threadIdx.x == 0) q->acc = 0;
 }
 
 __global__ __launch_bounds__(256) void k_scatter_items(const uint8_t *bucket, uint32_t nA,
-                                                       QueueState *q, uint32_t *items) {
-    __shared__ uint32_t hist[NBUCKET], base[NBUCKET];
-    for (int i = threadIdx.x; i < NBUCKET; i += blockDim.x) hist[i] = 0;
+                                                       QueueState *q, uint32_t *items,
+                                                       uint32_t *items_wide) {
+    __shared__ uint32_t hist[2][NBUCKET], base[2][NBUCKET];
+    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
     __syncthreads();
     uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t b = 0, local = 0;
+    uint32_t b = 0, cls = 0, local = 0;
     if (u < nA) {
-        b = bucket[u];
-        if (b) local = atomicAdd(&hist[b], 1u);
+        b = bucket[u] & 127u;
+        cls = bucket[u] >> 7;
+        if (b) local = atomicAdd(&hist[cls][b], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < NBUCKET; i += blockDim.x)
-        if (hist[i]) base[i] = atomicAdd(&q->cursor[i], hist[i]);
+    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) {
+        uint32_t h = (&hist[0][0])[i];
+        if (h) (&base[0][0])[i] = atomicAdd(&(&q->cursor[0][0])[i], h);
+    }
     __syncthreads();
-    if (b) items[base[b] + local] = u;
+    if (b) (cls ? items_wide : items)[base[cls][b] + local] = u;
 }
 
 __global__ void k_zero_u32(uint32_t *p, uint64_t n) {
@@ -196,460 +198,506 @@ __global__ void k_zero_u32(uint32_t *p, uint64_t n) {
         p[i] = 0;
 }
 
-// ------------------------------------------------------------------ the count
+__global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// End of a persistent launch over class `cls`: add this workgroup's sum; the
+// last workgroup to finish re-arms the class's queue for the next launch and,
+// when `total` is given, publishes the count and clears the accumulator.
+__device__ inline void finish_launch(QueueState *q, int cls, unsigned long long part,
+                                     unsigned long long *total) {
+    if (threadIdx.x != 0) return;
+    if (part) atomicAdd(&q->acc, part);
+    __threadfence();
+    uint32_t d = atomicAdd(&q->done[cls], 1u);
+    if (d == gridDim.x - 1) {
+        __threadfence();
+        if (total) {
+            *total = atomicAdd(&q->acc, 0ull);
+            q->acc = 0;
+        }
+        q->head[cls] = 0;
+        q->done[cls] = 0;
+        __threadfence();
+    }
+}
+
 struct CountArgs {
     const uint32_t *offA, *adjA, *xA, *offB, *adjB;
     const uint32_t *seg1, *seg_start, *seg_win;
-    const uint32_t *items;
+    const uint32_t *items, *items_wide;
     QueueState *q;
     uint32_t nA;
     unsigned long long *total;
 };
 
-struct Shared {
-    uint32_t tbl[TBL_BYTES / 4];
-    uint32_t pre[NT];
-    uint32_t lo[NT];
-    uint32_t hi[NT];
-    uint32_t red[NT / WAVE + 1];
-    unsigned long long red64[NT / WAVE];
-    uint32_t item;
-};
-
-__device__ inline void clear_table(Shared &sh) {
-    uint4 z = make_uint4(0, 0, 0, 0);
-    for (int i = threadIdx.x; i < TBL_BYTES / 16; i += NT) ((uint4 *)sh.tbl)[i] = z;
-}
-
-// Byte counters: add one to counter `off` and return its previous value.
-__device__ inline uint32_t bump8(Shared &sh, uint32_t off) {
-    uint32_t sh8 = (off & 3u) << 3;
-    uint32_t old = atomicAdd(&sh.tbl[off >> 2], 1u << sh8);
-    return (old >> sh8) & 0xFFu;
-}
-
-__device__ inline void group_bump8(Shared &sh, uint4 q, uint32_t base, uint32_t lo, uint32_t hi,
-                                   uint32_t win_base, unsigned long long &sum) {
-    uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        uint32_t pos = base + i;
-        if (pos >= lo && pos < hi) sum += bump8(sh, w[i] - win_base);
-    }
-}
-
-__device__ inline void group_clear8(Shared &sh, uint4 q, uint32_t base, uint32_t lo, uint32_t hi,
-                                    uint32_t win_base) {
-    uint32_t w[4] = {q.x, q.y, q.z, q.w};
-    uint8_t *t8 = (uint8_t *)sh.tbl;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        uint32_t pos = base + i;
-        if (pos >= lo && pos < hi) t8[w[i] - win_base] = 0;
-    }
-}
-
-// One start with d_u < NT: one midpoint per lane, byte counters, windows of
-// 2^16 ranks visited in increasing order, empty windows skipped.
-__device__ unsigned long long count_narrow(const CountArgs &a, Shared &sh, uint32_t rb,
-                                           uint32_t du) {
-    const uint32_t tid = threadIdx.x;
-    uint32_t p = 0, ev = 0, cur = 0, win = INF;
-    if (tid < du) {
-        uint32_t k = rb + tid;
-        uint32_t v = a.adjA[k];
-        p = a.xA[k] + 1;
-        ev = a.offB[v + 1];
-        if (p < ev) {
-            cur = a.seg1[p] - 1;
-            win = a.seg_win[cur];
-        }
-    }
-    unsigned long long sum = 0;
-    for (;;) {
-        const uint32_t kw = block_min<NT>(win, sh.red);
-        if (kw == INF) break;
-        uint32_t lo = 0, hi = 0, nch = 0;
-        if (win == kw) {
-            lo = p;
-            uint32_t e = a.seg_start[cur + 1];
-            hi = e < ev ? e : ev;
-            nch = ((hi + 3) >> 2) - (lo >> 2);
-            p = hi;
-            if (p < ev) {
-                cur++;
-                win = a.seg_win[cur];
-            } else {
-                win = INF;
-            }
-        }
-        uint32_t C;
-        uint32_t ex = block_excl_scan<NT>(nch, sh.red, &C);
-        sh.pre[tid] = ex;
-        sh.lo[tid] = lo;
-        sh.hi[tid] = hi;
-        __syncthreads();
-        const uint32_t wb = kw << G_SHIFT;
-        uint4 kq[KEEP];
-        uint32_t kb[KEEP], kl[KEEP], kh[KEEP];
-#pragma unroll
-        for (int r = 0; r < KEEP; r++) {
-            uint32_t c = tid + r * NT;
-            kl[r] = kh[r] = kb[r] = 0;
-            kq[r] = make_uint4(0, 0, 0, 0);
-            if (c < C) {
-                uint32_t j = upper_bound_lds(sh.pre, du, c) - 1;
-                kl[r] = sh.lo[j];
-                kh[r] = sh.hi[j];
-                kb[r] = ((kl[r] >> 2) + (c - sh.pre[j])) << 2;
-                kq[r] = *(const uint4 *)(a.adjB + kb[r]);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < KEEP; r++) group_bump8(sh, kq[r], kb[r], kl[r], kh[r], wb, sum);
-        for (uint32_t c = tid + KEEP * NT; c < C; c += NT) {
-            uint32_t j = upper_bound_lds(sh.pre, du, c) - 1;
-            uint32_t l = sh.lo[j], h = sh.hi[j];
-            uint32_t b = ((l >> 2) + (c - sh.pre[j])) << 2;
-            uint4 q = *(const uint4 *)(a.adjB + b);
-            group_bump8(sh, q, b, l, h, wb, sum);
-        }
-        __syncthreads();
-        if (C <= (uint32_t)(KEEP * NT)) {
-#pragma unroll
-            for (int r = 0; r < KEEP; r++) group_clear8(sh, kq[r], kb[r], kl[r], kh[r], wb);
-        } else {
-            clear_table(sh);
-        }
-        __syncthreads();
-    }
-    return sum;
-}
-
-// One start with d_u >= NT: 32-bit counters over windows of 2^14 ranks,
-// midpoints in batches of NT, sub-runs found by binary search.
-__device__ unsigned long long count_wide(const CountArgs &a, Shared &sh, uint32_t u, uint32_t rb,
-                                         uint32_t du) {
-    const uint32_t tid = threadIdx.x;
-    unsigned long long sum = 0;
-    if (u + 1 >= a.nA) return 0;
-    const uint32_t w_first = (u + 1) >> W32_SHIFT, w_last = (a.nA - 1) >> W32_SHIFT;
-    for (uint32_t kw = w_first; kw <= w_last; kw++) {
-        const uint32_t wb = kw << W32_SHIFT;
-        const uint32_t we = wb + (1u << W32_SHIFT);
-        for (uint32_t mb = 0; mb < du; mb += NT) {
-            uint32_t lo = 0, hi = 0, nch = 0;
-            if (mb + tid < du) {
-                uint32_t k = rb + mb + tid;
-                uint32_t v = a.adjA[k];
-                uint32_t p = a.xA[k] + 1, ev = a.offB[v + 1];
-                if (p < ev) {
-                    lo = lower_bound_glb(a.adjB, p, ev, wb);
-                    hi = lower_bound_glb(a.adjB, lo, ev, we);
-                    if (hi > lo) nch = ((hi + 3) >> 2) - (lo >> 2);
-                }
-            }
-            uint32_t C;
-            uint32_t ex = block_excl_scan<NT>(nch, sh.red, &C);
-            sh.pre[tid] = ex;
-            sh.lo[tid] = lo;
-            sh.hi[tid] = hi;
-            __syncthreads();
-            for (uint32_t c = tid; c < C; c += NT) {
-                uint32_t j = upper_bound_lds(sh.pre, NT, c) - 1;
-                uint32_t l = sh.lo[j], h = sh.hi[j];
-                uint32_t b = ((l >> 2) + (c - sh.pre[j])) << 2;
-                uint4 q = *(const uint4 *)(a.adjB + b);
-                uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    uint32_t pos = b + i;
-                    if (pos >= l && pos < h) sum += atomicAdd(&sh.tbl[w[i] - wb], 1u);
-                }
-            }
-            __syncthreads();
-        }
-        clear_table(sh);
-        __syncthreads();
-    }
-    return sum;
-}
-
-__global__ __launch_bounds__(NT) void k_exact(CountArgs a) {
-    __shared__ Shared sh;
-    clear_table(sh);
-    __syncthreads();
-    unsigned long long acc = 0;
-    const uint32_t n_items = a.q->n_items;
-    for (;;) {
-        if (threadIdx.x == 0) sh.item = atomicAdd(&a.q->head, 1u);
-        __syncthreads();
-        const uint32_t it = sh.item;
-        __syncthreads();
-        if (it >= n_items) break;
-        const uint32_t u = a.items[it];
-        const uint32_t rb = a.offA[u], du = a.offA[u + 1] - rb;
-        if (du < (uint32_t)NT) acc += count_narrow(a, sh, rb, du);
-        else acc += count_wide(a, sh, u, rb, du);
-    }
-    acc = block_sum64<NT>(acc, sh.red64);
-    finish_launch(a.q, acc, a.total);
-}
-
-// ------------------------------------------------------------------ local counts
-// For a start u the walk takes every endpoint w != u (no order), so C_u[w] =
-// |N(u) & N(w)| for all same-side w and
+// Local counts.  For a start u the walk takes every endpoint w != u (no
+// order), so C_u[w] = |N(u) & N(w)| for all same-side w and
 //   B_u       = sum_w C(C_u[w], 2)                       (Eq. (2))
 //   B_(u,v)   = sum_{w in N(v), w != u} (C_u[w] - 1)       (edge definition)
 //   B_v (mid) = 1/2 sum_{u in N(v)} B_(u,v)               (two edges of v per butterfly)
-// The first sum runs during the increments; after a window's increments the
-// same entries are read again and summed per midpoint.
+// After a window's increments the final counts of its entries are read again
+// and summed per midpoint.
 struct LocalArgs {
     CountArgs c;
     const uint32_t *eidA, *idA;
     unsigned long long *cntA;     // per start-side vertex (caller ids), or null
     unsigned long long *cntE;     // per edge (caller order), or null
     unsigned long long *twiceB;   // 2 B_v per midpoint rank (workspace)
-    unsigned long long *esum;     // per A-side CSR position (workspace, wide starts)
+    unsigned long long *esum;     // per A-side adjacency position (wide starts)
 };
 
-struct LocalShared {
-    Shared s;
-    uint32_t x[NT];
-    unsigned long long esum[NT];
+// Per-edge and per-midpoint output of one (start, midpoint) pair.
+__device__ inline void emit_edge(const LocalArgs &a, uint32_t k, uint32_t v, uint32_t dv,
+                                 unsigned long long s) {
+    unsigned long long e = s - (unsigned long long)(dv - 1);
+    if (a.cntE) a.cntE[a.eidA[k]] = e;
+    if (e) atomicAdd(&a.twiceB[v], e);
+}
+
+// A group: 4 consecutive adjacency entries at `base` (16-byte aligned), of
+// which those in [lo, hi) other than `skip` belong to the sub-run.
+__device__ inline uint32_t group_mask(uint32_t base, uint32_t lo, uint32_t hi, uint32_t skip) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        uint32_t pos = base + i;
+        m |= (uint32_t)(pos >= lo && pos < hi && pos != skip) << i;
+    }
+    return m;
+}
+
+// ------------------------------------------------------------------ narrow: one wave per start
+// A window's sub-runs are cut into pieces of WK consecutive groups (16
+// entries) of one midpoint; lanes take pieces round-robin, so one search maps
+// a piece to its midpoint and the entries of a piece are contiguous.
+constexpr int WK = 4;
+
+template <bool LOCAL>
+struct WShared {
+    uint32_t tbl[WTBL_WORDS + WT];      // byte counters, then one zero word per lane
+    uint32_t pre[WSLOTS * WT];          // exclusive prefix of pieces per midpoint
+    uint32_t lo[WSLOTS * WT], hi[WSLOTS * WT];
+    uint32_t skip[LOCAL ? WSLOTS * WT : 1];
+    unsigned long long esum[LOCAL ? WSLOTS * WT : 1];
 };
 
-__device__ inline void group_read8(const Shared &sh, uint4 q, uint32_t base, uint32_t lo,
-                                   uint32_t hi, uint32_t skip, uint32_t win_base,
-                                   unsigned long long &acc) {
-    uint32_t w[4] = {q.x, q.y, q.z, q.w};
-    const uint8_t *t8 = (const uint8_t *)sh.tbl;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        uint32_t pos = base + i;
-        if (pos >= lo && pos < hi && pos != skip) acc += t8[w[i] - win_base];
+// One lane's piece: entries base .. base + 4*WK - 1, of which those with
+// pos - lo < len (and pos != skip) are in the sub-run.
+struct Piece {
+    uint32_t base, lo, len, skip, j;
+};
+
+template <bool LOCAL>
+__device__ inline Piece wpiece(const WShared<LOCAL> &sh, uint32_t du, uint32_t pi, bool valid) {
+    // branch-free search over the du midpoint prefixes (uniform trip count)
+    uint32_t j = 0;
+    for (uint32_t s = 1u << (31 - __clz(du)); s; s >>= 1) {
+        const uint32_t t = j + s;
+        const uint32_t pv = sh.pre[(t <= du ? t : du) - 1];
+        j = (t <= du && pv <= pi) ? t : j;
     }
+    j -= 1;
+    Piece pc;
+    const uint32_t lo = sh.lo[j], hi = sh.hi[j];
+    const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * WK;
+    const uint32_t end = min(hi, (g0 + WK) << 2);
+    pc.base = valid ? g0 << 2 : 0;
+    pc.lo = lo;
+    pc.len = valid ? end - lo : 0;
+    pc.skip = LOCAL ? sh.skip[j] : INF;
+    pc.j = j;
+    return pc;
 }
 
-__device__ inline void group_bump8_skip(Shared &sh, uint4 q, uint32_t base, uint32_t lo,
-                                        uint32_t hi, uint32_t skip, uint32_t win_base,
-                                        unsigned long long &sum) {
-    uint32_t w[4] = {q.x, q.y, q.z, q.w};
+template <int N>
+__device__ inline void wfetch(const uint32_t *adjB, const Piece &pc, uint4 *q) {
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        uint32_t pos = base + i;
-        if (pos >= lo && pos < hi && pos != skip) sum += bump8(sh, w[i] - win_base);
-    }
+    for (int k = 0; k < N; k++) q[k] = *(const uint4 *)(adjB + pc.base + 4 * k);
 }
 
-__device__ inline void group_clear8_skip(Shared &sh, uint4 q, uint32_t base, uint32_t lo,
-                                         uint32_t hi, uint32_t skip, uint32_t win_base) {
-    uint32_t w[4] = {q.x, q.y, q.z, q.w};
-    uint8_t *t8 = (uint8_t *)sh.tbl;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        uint32_t pos = base + i;
-        if (pos >= lo && pos < hi && pos != skip) t8[w[i] - win_base] = 0;
-    }
+// Entry i of the piece -> byte offset of its counter, or of the lane's zero
+// word when it is not in the sub-run.
+__device__ inline uint32_t wslot(const Piece &pc, uint32_t i, uint32_t w, uint32_t wb,
+                                 uint32_t zero_byte) {
+    const uint32_t pos = pc.base + i;
+    const bool on = (pos - pc.lo) < pc.len && pos != pc.skip;
+    return on ? w - wb : zero_byte;
 }
 
-__device__ void local_narrow(const LocalArgs &a, LocalShared &ls, uint32_t u, uint32_t rb,
-                             uint32_t du) {
-    Shared &sh = ls.s;
-    const CountArgs &c = a.c;
-    const uint32_t tid = threadIdx.x;
-    uint32_t p = 0, ev = 0, cur = 0, win = INF, v = 0, x = 0;
-    if (tid < du) {
-        uint32_t k = rb + tid;
-        v = c.adjA[k];
-        x = c.xA[k];
-        p = c.offB[v];
-        ev = c.offB[v + 1];
-        if (ev - p > 1) {                 // some endpoint other than u
-            cur = c.seg1[p] - 1;
-            win = c.seg_win[cur];
+// Add one to every counter of the piece; the counters' previous values are
+// what the pairs gain.  A zero word gets a zero increment and returns zero.
+template <bool LOCAL>
+__device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
+    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * 4;
+    uint32_t old[4 * WK], sft[4 * WK];
+#pragma unroll
+    for (int k = 0; k < WK; k++) {
+        const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint32_t b = wslot(pc, 4 * k + i, w[i], wb, zb);
+            const uint32_t s8 = (b & 3u) << 3;
+            sft[4 * k + i] = s8;
+            old[4 * k + i] = atomicAdd(&sh.tbl[b >> 2], (uint32_t)(b != zb) << s8);
         }
-        ls.x[tid] = x;
     }
-    ls.esum[tid] = 0;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4 * WK; k++) s += (old[k] >> sft[k]) & 0xFFu;
+    return s;
+}
+
+// Sum of the counters of the piece's entries.
+template <bool LOCAL>
+__device__ inline uint32_t wread(const WShared<LOCAL> &sh, const Piece &pc, const uint4 *q,
+                                 uint32_t wb) {
+    const uint8_t *t8 = (const uint8_t *)sh.tbl;
+    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * 4;
+    uint32_t v[4 * WK];
+#pragma unroll
+    for (int k = 0; k < WK; k++) {
+        const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[4 * k + i] = t8[wslot(pc, 4 * k + i, w[i], wb, zb)];
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4 * WK; k++) s += v[k];
+    return s;
+}
+
+template <bool LOCAL>
+__device__ inline void wclear(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
+    uint8_t *t8 = (uint8_t *)sh.tbl;
+    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * 4;
+#pragma unroll
+    for (int k = 0; k < WK; k++) {
+        const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+        for (int i = 0; i < 4; i++) t8[wslot(pc, 4 * k + i, w[i], wb, zb)] = 0;
+    }
+}
+
+template <bool LOCAL>
+__device__ inline void wclear_all(WShared<LOCAL> &sh) {
+    const uint4 z = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < WTBL_BYTES / 16 / WT; i++) ((uint4 *)sh.tbl)[i * WT + threadIdx.x] = z;
+}
+
+// Walk of one narrow start by one wave.  Lane l owns midpoints l + 64 s.
+// EXACT: endpoints ranked above u.  LOCAL: all endpoints other than u, with
+// the per-midpoint sums of final counts accumulated in sh.esum.
+template <bool LOCAL>
+__device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, uint32_t rb,
+                                        uint32_t du) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t ns = (du + WT - 1) / WT;
+    uint32_t p[WSLOTS], ev[WSLOTS], cur[WSLOTS], win[WSLOTS], sn[WSLOTS], w2[WSLOTS], s2[WSLOTS];
+#pragma unroll
+    for (int s = 0; s < WSLOTS; s++) {
+        p[s] = ev[s] = cur[s] = sn[s] = s2[s] = 0;
+        win[s] = w2[s] = INF;
+        uint32_t skip = INF;
+        const uint32_t j = lane + s * WT;
+        if (s < (int)ns && j < du) {
+            const uint32_t k = rb + j;
+            const uint32_t v = a.adjA[k];
+            const uint32_t x = a.xA[k];
+            const uint32_t pb = a.offB[v];
+            ev[s] = a.offB[v + 1];
+            p[s] = LOCAL ? pb : x + 1;
+            if (LOCAL) skip = x;
+            if (LOCAL ? (ev[s] - pb > 1) : (p[s] < ev[s])) {
+                cur[s] = a.seg1[p[s]] - 1;
+                win[s] = a.seg_win[cur[s]];
+                sn[s] = a.seg_start[cur[s] + 1];
+                if (sn[s] < ev[s]) {
+                    w2[s] = a.seg_win[cur[s] + 1];
+                    s2[s] = a.seg_start[cur[s] + 2];
+                }
+            }
+        }
+        if (LOCAL) {
+            sh.skip[j] = skip;
+            sh.esum[j] = 0;
+        }
+    }
     unsigned long long sum = 0;
     for (;;) {
-        const uint32_t kw = block_min<NT>(win, sh.red);
+        uint32_t mn = INF;
+#pragma unroll
+        for (int s = 0; s < WSLOTS; s++) mn = min(mn, win[s]);
+        const uint32_t kw = wave_min(mn);
         if (kw == INF) break;
-        uint32_t lo = 0, hi = 0, nch = 0;
-        if (win == kw) {
-            lo = p;
-            uint32_t e = c.seg_start[cur + 1];
-            hi = e < ev ? e : ev;
-            nch = ((hi + 3) >> 2) - (lo >> 2);
-            p = hi;
-            if (p < ev) {
-                cur++;
-                win = c.seg_win[cur];
-            } else {
-                win = INF;
+        // sub-runs of this window and the prefix sums of their pieces
+        uint32_t run = 0;
+#pragma unroll
+        for (int s = 0; s < WSLOTS; s++) {
+            if (s >= (int)ns) break;
+            uint32_t lo = 0, hi = 0, np = 0;
+            if (win[s] == kw) {
+                lo = p[s];
+                hi = sn[s] < ev[s] ? sn[s] : ev[s];
+                np = (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK;
+                p[s] = hi;
+                if (p[s] < ev[s]) {
+                    cur[s]++;
+                    win[s] = w2[s];
+                    sn[s] = s2[s];
+                    if (sn[s] < ev[s]) {
+                        w2[s] = a.seg_win[cur[s] + 1];
+                        s2[s] = a.seg_start[cur[s] + 2];
+                    }
+                } else {
+                    win[s] = INF;
+                }
             }
+            const uint32_t inc = wave_incl_scan(np);
+            const uint32_t j = lane + s * WT;
+            sh.pre[j] = run + inc - np;
+            sh.lo[j] = lo;
+            sh.hi[j] = hi;
+            run += __shfl(inc, WT - 1, WT);
         }
-        uint32_t C;
-        uint32_t ex = block_excl_scan<NT>(nch, sh.red, &C);
-        sh.pre[tid] = ex;
-        sh.lo[tid] = lo;
-        sh.hi[tid] = hi;
+        const uint32_t NP = run;
         __syncthreads();
         const uint32_t wb = kw << G_SHIFT;
-        uint4 kq[KEEP];
-        uint32_t kb[KEEP], kj[KEEP];
-        bool kv[KEEP];
-#pragma unroll
-        for (int r = 0; r < KEEP; r++) {
-            uint32_t cc = tid + r * NT;
-            kv[r] = cc < C;
-            kb[r] = kj[r] = 0;
-            kq[r] = make_uint4(0, 0, 0, 0);
-            if (kv[r]) {
-                uint32_t j = upper_bound_lds(sh.pre, du, cc) - 1;
-                kj[r] = j;
-                kb[r] = ((sh.lo[j] >> 2) + (cc - sh.pre[j])) << 2;
-                kq[r] = *(const uint4 *)(c.adjB + kb[r]);
+        uint32_t part = 0;
+        if (NP <= (uint32_t)WT) {
+            // one piece per lane: keep it in registers for the second look
+            // and the clear
+            const Piece pc = wpiece(sh, du, lane, lane < NP);
+            uint4 q[WK];
+            wfetch<WK>(a.adjB, pc, q);
+            part = wbump(sh, pc, q, wb);
+            if (LOCAL) {
+                __syncthreads();
+                const uint32_t v = wread(sh, pc, q, wb);
+                if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
             }
-        }
-#pragma unroll
-        for (int r = 0; r < KEEP; r++)
-            if (kv[r]) {
-                uint32_t j = kj[r];
-                group_bump8_skip(sh, kq[r], kb[r], sh.lo[j], sh.hi[j], ls.x[j], wb, sum);
-            }
-        for (uint32_t cc = tid + KEEP * NT; cc < C; cc += NT) {
-            uint32_t j = upper_bound_lds(sh.pre, du, cc) - 1;
-            uint32_t b = ((sh.lo[j] >> 2) + (cc - sh.pre[j])) << 2;
-            uint4 q = *(const uint4 *)(c.adjB + b);
-            group_bump8_skip(sh, q, b, sh.lo[j], sh.hi[j], ls.x[j], wb, sum);
-        }
-        __syncthreads();
-        // second look: final counts of this window, summed per midpoint
-#pragma unroll
-        for (int r = 0; r < KEEP; r++)
-            if (kv[r]) {
-                uint32_t j = kj[r];
-                unsigned long long acc = 0;
-                group_read8(sh, kq[r], kb[r], sh.lo[j], sh.hi[j], ls.x[j], wb, acc);
-                if (acc) atomicAdd(&ls.esum[j], acc);
-            }
-        for (uint32_t cc = tid + KEEP * NT; cc < C; cc += NT) {
-            uint32_t j = upper_bound_lds(sh.pre, du, cc) - 1;
-            uint32_t b = ((sh.lo[j] >> 2) + (cc - sh.pre[j])) << 2;
-            uint4 q = *(const uint4 *)(c.adjB + b);
-            unsigned long long acc = 0;
-            group_read8(sh, q, b, sh.lo[j], sh.hi[j], ls.x[j], wb, acc);
-            if (acc) atomicAdd(&ls.esum[j], acc);
-        }
-        __syncthreads();
-        if (C <= (uint32_t)(KEEP * NT)) {
-#pragma unroll
-            for (int r = 0; r < KEEP; r++)
-                if (kv[r]) {
-                    uint32_t j = kj[r];
-                    group_clear8_skip(sh, kq[r], kb[r], sh.lo[j], sh.hi[j], ls.x[j], wb);
-                }
+            __syncthreads();
+            wclear(sh, pc, q, wb);
         } else {
-            clear_table(sh);
+            const uint32_t rounds = (NP + WT - 1) / WT;
+            for (uint32_t r = 0; r < rounds; r++) {
+                const uint32_t pi = lane + r * WT;
+                const Piece pc = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
+                uint4 q[WK];
+                wfetch<WK>(a.adjB, pc, q);
+                part += wbump(sh, pc, q, wb);
+            }
+            if (LOCAL) {
+                __syncthreads();
+                for (uint32_t r = 0; r < rounds; r++) {
+                    const uint32_t pi = lane + r * WT;
+                    const Piece pc = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
+                    uint4 q[WK];
+                    wfetch<WK>(a.adjB, pc, q);
+                    const uint32_t v = wread(sh, pc, q, wb);
+                    if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
+                }
+            }
+            __syncthreads();
+            wclear_all(sh);
         }
+        sum += part;
         __syncthreads();
     }
-    if (tid < du) {
-        unsigned long long e = ls.esum[tid] - (unsigned long long)(ev - c.offB[v] - 1);
-        if (a.cntE) a.cntE[a.eidA[rb + tid]] = e;
-        if (e) atomicAdd(&a.twiceB[v], e);
-    }
-    sum = block_sum64<NT>(sum, sh.red64);
-    if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = sum;
+    return sum;
 }
 
-__device__ void local_wide(const LocalArgs &a, LocalShared &ls, uint32_t u, uint32_t rb,
-                           uint32_t du) {
-    Shared &sh = ls.s;
-    const CountArgs &c = a.c;
+// Hand out WCHUNK starts per queue access.
+__device__ inline uint32_t wave_take(QueueState *q, int cls) {
+    uint32_t b = 0;
+    if (threadIdx.x == 0) b = atomicAdd(&q->head[cls], (uint32_t)WCHUNK);
+    return __shfl(b, 0, WT);
+}
+
+__global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
+    __shared__ WShared<false> sh;
+    wclear_all(sh);
+    sh.tbl[WTBL_WORDS + threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = a.q->n_items[0];
+    unsigned long long acc = 0;
+    for (uint32_t b = wave_take(a.q, 0); b < n; b = wave_take(a.q, 0)) {
+        const uint32_t e = b + WCHUNK < n ? b + WCHUNK : n;
+        for (uint32_t it = b; it < e; it++) {
+            const uint32_t u = a.items[it];
+            const uint32_t rb = a.offA[u];
+            acc += wave_walk<false>(a, sh, rb, a.offA[u + 1] - rb);
+        }
+    }
+    acc = wave_sum64(acc);
+    finish_launch(a.q, 0, acc, nullptr);
+}
+
+__global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
+    __shared__ WShared<true> sh;
+    wclear_all(sh);
+    sh.tbl[WTBL_WORDS + threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = a.c.q->n_items[0];
+    for (uint32_t b = wave_take(a.c.q, 0); b < n; b = wave_take(a.c.q, 0)) {
+        const uint32_t e = b + WCHUNK < n ? b + WCHUNK : n;
+        for (uint32_t it = b; it < e; it++) {
+            const uint32_t u = a.c.items[it];
+            const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
+            unsigned long long s = wave_walk<true>(a.c, sh, rb, du);
+            for (uint32_t j = threadIdx.x; j < du; j += WT) {
+                const uint32_t k = rb + j;
+                const uint32_t v = a.c.adjA[k];
+                emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], sh.esum[j]);
+            }
+            s = wave_sum64(s);
+            if (threadIdx.x == 0 && a.cntA) a.cntA[a.idA[u]] = s;
+            __syncthreads();
+        }
+    }
+    finish_launch(a.c.q, 0, 0, nullptr);
+}
+
+// ------------------------------------------------------------------ wide: workgroup per start
+struct Shared {
+    uint32_t tbl[TBL_WORDS];
+    uint32_t pre[MIDS], lo[MIDS], hi[MIDS], skip[MIDS];
+    unsigned long long esum[MIDS];
+    uint32_t red[NT / WAVE + 1];
+    unsigned long long red64[NT / WAVE];
+    uint32_t item;
+};
+
+__device__ inline void clear_table(Shared &sh) {
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    for (int i = threadIdx.x; i < TBL_WORDS / 4; i += NT) ((uint4 *)sh.tbl)[i] = z;
+}
+
+// Group c of the batch -> midpoint, position and mask (LDS binary search).
+__device__ inline uint32_t locate(const Shared &sh, uint32_t nmid, uint32_t c, uint32_t &base,
+                                  uint32_t &mask) {
+    const uint32_t j = upper_bound_lds(sh.pre, nmid, c) - 1;
+    const uint32_t lo = sh.lo[j];
+    base = ((lo >> 2) + (c - sh.pre[j])) << 2;
+    mask = group_mask(base, lo, sh.hi[j], sh.skip[j]);
+    return j;
+}
+
+// One start with d_u > 255: 32-bit counters over windows of 2^14 ranks,
+// midpoints in batches of MIDS, sub-runs found by binary search.  LOCAL runs a
+// second pass per window that sums the final counts per midpoint into
+// esum_g (one slot per A-side adjacency position).
+template <bool LOCAL>
+__device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t u, uint32_t rb,
+                                        uint32_t du, unsigned long long *esum_g) {
     const uint32_t tid = threadIdx.x;
     unsigned long long sum = 0;
-    for (uint32_t mb = tid; mb < du; mb += NT) a.esum[rb + mb] = 0;
-    const uint32_t w_last = (c.nA - 1) >> W32_SHIFT;
-    for (uint32_t kw = 0; kw <= w_last; kw++) {
-        const uint32_t wb = kw << W32_SHIFT;
-        const uint32_t we = wb + (1u << W32_SHIFT);
-        for (int pass = 0; pass < 2; pass++) {
-            for (uint32_t mb = 0; mb < du; mb += NT) {
-                uint32_t lo = 0, hi = 0, nch = 0, x = 0;
-                if (mb + tid < du) {
-                    uint32_t k = rb + mb + tid;
-                    uint32_t v = c.adjA[k];
-                    uint32_t pb = c.offB[v], ev = c.offB[v + 1];
-                    x = c.xA[k];
-                    lo = lower_bound_glb(c.adjB, pb, ev, wb);
-                    hi = lower_bound_glb(c.adjB, lo, ev, we);
-                    if (hi > lo) nch = ((hi + 3) >> 2) - (lo >> 2);
+    if (LOCAL) {
+        for (uint32_t j = tid; j < du; j += NT) esum_g[rb + j] = 0;
+    } else if (u + 1 >= a.nA) {
+        return 0;
+    }
+    const uint32_t w_first = LOCAL ? 0 : (u + 1) >> G_SHIFT;
+    const uint32_t w_last = (a.nA - 1) >> G_SHIFT;
+    for (uint32_t kw = w_first; kw <= w_last; kw++) {
+        const uint32_t wb = kw << G_SHIFT;
+        const uint32_t we = wb + (1u << G_SHIFT);
+        for (int pass = 0; pass < (LOCAL ? 2 : 1); pass++) {
+            for (uint32_t mb = 0; mb < du; mb += MIDS) {
+                uint32_t lo = 0, hi = 0, nch = 0, skip = INF;
+                if (tid < MIDS && mb + tid < du) {
+                    const uint32_t k = rb + mb + tid;
+                    const uint32_t v = a.adjA[k];
+                    const uint32_t x = a.xA[k];
+                    const uint32_t ev = a.offB[v + 1];
+                    const uint32_t p = LOCAL ? a.offB[v] : x + 1;
+                    if (LOCAL) skip = x;
+                    if (p < ev) {
+                        lo = lower_bound_glb(a.adjB, p, ev, wb);
+                        hi = lower_bound_glb(a.adjB, lo, ev, we);
+                        if (hi > lo) nch = ((hi + 3) >> 2) - (lo >> 2);
+                    }
                 }
                 uint32_t C;
-                uint32_t ex = block_excl_scan<NT>(nch, sh.red, &C);
-                sh.pre[tid] = ex;
-                sh.lo[tid] = lo;
-                sh.hi[tid] = hi;
-                ls.x[tid] = x;
-                ls.esum[tid] = 0;
+                const uint32_t ex = block_excl_scan<NT>(nch, sh.red, &C);
+                if (tid < MIDS) {
+                    sh.pre[tid] = ex;
+                    sh.lo[tid] = lo;
+                    sh.hi[tid] = hi;
+                    sh.skip[tid] = skip;
+                    if (LOCAL) sh.esum[tid] = 0;
+                }
                 __syncthreads();
-                uint32_t nm = du - mb < (uint32_t)NT ? du - mb : (uint32_t)NT;
-                for (uint32_t cc = tid; cc < C; cc += NT) {
-                    uint32_t j = upper_bound_lds(sh.pre, nm, cc) - 1;
-                    uint32_t l = sh.lo[j], h = sh.hi[j], sk = ls.x[j];
-                    uint32_t b = ((l >> 2) + (cc - sh.pre[j])) << 2;
-                    uint4 q = *(const uint4 *)(c.adjB + b);
-                    uint32_t w[4] = {q.x, q.y, q.z, q.w};
+                const uint32_t nm = du - mb < (uint32_t)MIDS ? du - mb : (uint32_t)MIDS;
+                for (uint32_t c = tid; c < C; c += NT) {
+                    uint32_t base, mask;
+                    const uint32_t j = locate(sh, nm, c, base, mask);
+                    const uint4 g = *(const uint4 *)(a.adjB + base);
+                    const uint32_t w[4] = {g.x, g.y, g.z, g.w};
                     unsigned long long acc = 0;
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
-                        uint32_t pos = b + i;
-                        if (pos >= l && pos < h && pos != sk) {
-                            if (pass == 0) sum += atomicAdd(&sh.tbl[w[i] - wb], 1u);
-                            else acc += sh.tbl[w[i] - wb];
-                        }
+                        if (!(mask >> i & 1)) continue;
+                        if (pass == 0) sum += atomicAdd(&sh.tbl[w[i] - wb], 1u);
+                        else acc += sh.tbl[w[i] - wb];
                     }
-                    if (pass == 1 && acc) atomicAdd(&ls.esum[j], acc);
+                    if (LOCAL && pass == 1 && acc) atomicAdd(&sh.esum[j], acc);
                 }
                 __syncthreads();
-                if (pass == 1 && mb + tid < du) a.esum[rb + mb + tid] += ls.esum[tid];
+                if (LOCAL && pass == 1 && tid < MIDS && mb + tid < du)
+                    esum_g[rb + mb + tid] += sh.esum[tid];
                 __syncthreads();
             }
         }
         clear_table(sh);
         __syncthreads();
     }
-    for (uint32_t j = tid; j < du; j += NT) {
-        uint32_t k = rb + j;
-        uint32_t v = c.adjA[k];
-        unsigned long long e = a.esum[k] - (unsigned long long)(c.offB[v + 1] - c.offB[v] - 1);
-        if (a.cntE) a.cntE[a.eidA[k]] = e;
-        if (e) atomicAdd(&a.twiceB[v], e);
-    }
-    sum = block_sum64<NT>(sum, sh.red64);
-    if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = sum;
+    return sum;
 }
 
-__global__ __launch_bounds__(NT) void k_local(LocalArgs a) {
-    __shared__ LocalShared ls;
-    clear_table(ls.s);
+__device__ inline uint32_t block_take(Shared &sh, QueueState *q) {
     __syncthreads();
-    const uint32_t n_items = a.c.q->n_items;
-    for (;;) {
-        if (threadIdx.x == 0) ls.s.item = atomicAdd(&a.c.q->head, 1u);
-        __syncthreads();
-        const uint32_t it = ls.s.item;
-        __syncthreads();
-        if (it >= n_items) break;
-        const uint32_t u = a.c.items[it];
-        const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
-        if (du < (uint32_t)NT) local_narrow(a, ls, u, rb, du);
-        else local_wide(a, ls, u, rb, du);
+    if (threadIdx.x == 0) sh.item = atomicAdd(&q->head[1], 1u);
+    __syncthreads();
+    return sh.item;
+}
+
+__global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a) {
+    __shared__ Shared sh;
+    clear_table(sh);
+    const uint32_t n = a.q->n_items[1];
+    unsigned long long acc = 0;
+    for (uint32_t it = block_take(sh, a.q); it < n; it = block_take(sh, a.q)) {
+        const uint32_t u = a.items_wide[it];
+        const uint32_t rb = a.offA[u];
+        acc += walk_wide<false>(a, sh, u, rb, a.offA[u + 1] - rb, nullptr);
     }
-    finish_launch(a.c.q, 0, nullptr);
+    acc = block_sum64<NT>(acc, sh.red64);
+    finish_launch(a.q, 1, acc, a.total);
+}
+
+__global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a) {
+    __shared__ Shared sh;
+    clear_table(sh);
+    const uint32_t n = a.c.q->n_items[1];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t it = block_take(sh, a.c.q); it < n; it = block_take(sh, a.c.q)) {
+        const uint32_t u = a.c.items_wide[it];
+        const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
+        unsigned long long s = walk_wide<true>(a.c, sh, u, rb, du, a.esum);
+        for (uint32_t j = tid; j < du; j += NT) {
+            const uint32_t k = rb + j;
+            const uint32_t v = a.c.adjA[k];
+            emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], a.esum[k]);
+        }
+        s = block_sum64<NT>(s, sh.red64);
+        if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = s;
+    }
+    finish_launch(a.c.q, 1, 0, nullptr);
 }
 
 // B_v of the midpoint side from the edge sums; outputs in caller ids.
@@ -659,15 +707,9 @@ __global__ void k_local_finish(const unsigned long long *twiceB, const uint32_t 
         cntB[idB[v]] = twiceB[v] >> 1;
 }
 
-__global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
 // ------------------------------------------------------------------ host side
 struct ExactWs {
-    uint32_t *seg1, *seg_start, *seg_win, *scan_tmp, *items;
+    uint32_t *seg1, *seg_start, *seg_win, *scan_tmp, *items, *items_wide;
     uint8_t *bucket;
     QueueState *q;
 };
@@ -679,6 +721,7 @@ static ExactWs carve_exact(Carver &c, const Plan &p) {
     w.seg_win = c.take<uint32_t>(pad64(p.m));
     w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(p.m));
     w.items = c.take<uint32_t>(pad64(p.nA));
+    w.items_wide = c.take<uint32_t>(pad64(p.nA));
     w.bucket = c.take<uint8_t>(pad64(p.nA));
     w.q = c.take<QueueState>(1);
     return w;
@@ -693,17 +736,15 @@ static inline unsigned grid_for(uint64_t n, int nt = 256) {
 
 // Upper bound of the count: every start's pairs gain at most (d_u - 1) per
 // wedge / 2, so B <= wedges * (max start degree - 1) / 2.
-static bool overflow_risk(const Plan &p) {
-    if (p.max_deg_A < 2) return false;
-    unsigned __int128 b = (unsigned __int128)p.wedges * (p.max_deg_A - 1) / 2;
+static bool overflow_risk(uint64_t wedges, uint32_t max_deg) {
+    if (max_deg < 2) return false;
+    unsigned __int128 b = (unsigned __int128)wedges * (max_deg - 1) / 2;
     return b >> 64;
 }
 
-// Segments, per-start work buckets and the work queue for one plan.
-static int prepare(const Plan &p, ExactWs &w, unsigned long long *d_total, int all_ends,
-                   hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, (uint32_t *)w.q,
-                       (uint64_t)(sizeof(QueueState) / 4));
+// Segments, per-start work buckets and the work queues for one plan.
+static int prepare(const Plan &p, ExactWs &w, int all_ends, hipStream_t s) {
+    k_zero_u32<<<1, 256, 0, s>>>((uint32_t *)w.q, (uint64_t)(sizeof(QueueState) / 4));
     if (p.m) {
         k_seg_flags<<<grid_for(p.m), 256, 0, s>>>(p.adjB, p.m, w.seg1);
         k_seg_rowstarts<<<grid_for(p.nB), 256, 0, s>>>(p.offB, p.nB, w.seg1);
@@ -715,14 +756,55 @@ static int prepare(const Plan &p, ExactWs &w, unsigned long long *d_total, int a
     if (p.nA) {
         unsigned g = grid_for(p.nA, 4);
         if (g > 8192) g = 8192;
-        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.nA, all_ends, w.bucket,
-                                 w.q->bcount);
+        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.nA, all_ends, w.bucket, w.q);
         BFC_HIP(hipGetLastError());
     }
-    k_bucket_offsets<<<1, 64, 0, s>>>(w.q, d_total);
-    if (p.nA) k_scatter_items<<<grid_for(p.nA), 256, 0, s>>>(w.bucket, p.nA, w.q, w.items);
+    k_bucket_offsets<<<1, 64, 0, s>>>(w.q);
+    if (p.nA)
+        k_scatter_items<<<grid_for(p.nA), 256, 0, s>>>(w.bucket, p.nA, w.q, w.items, w.items_wide);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
+}
+
+static void fill_args(const Plan &p, const ExactWs &w, CountArgs &a) {
+    a.offA = p.offA; a.adjA = p.adjA; a.xA = p.xA; a.offB = p.offB; a.adjB = p.adjB;
+    a.seg1 = w.seg1; a.seg_start = w.seg_start; a.seg_win = w.seg_win;
+    a.items = w.items; a.items_wide = w.items_wide; a.q = w.q; a.nA = p.nA; a.total = nullptr;
+}
+
+// Waves of the narrow grid per CU (LDS bound) and workgroups of the wide grid.
+static int grids(unsigned &narrow, unsigned &wide) {
+    int dev = 0;
+    BFC_HIP(hipGetDevice(&dev));
+    const unsigned cu = (unsigned)device_cu_count(dev);
+    narrow = cu * 8;
+    wide = cu;
+    return BFC_OK;
+}
+
+static int exact_setup(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes, Plan &p,
+                       ExactWs &w) {
+    if (!d_ws) return BFC_E_NULL;
+    BFC_TRY(make_plan(g, side, &p));
+    if (!aligned256(d_ws)) return BFC_E_ALIGN;
+    if (overflow_risk(p.wedges, p.max_deg_A)) return BFC_E_OVERFLOW_RISK;
+    Carver c(d_ws, ws_bytes);
+    w = carve_exact(c, p);
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    return BFC_OK;
+}
+
+struct LocalWs {
+    ExactWs e;
+    unsigned long long *twiceB, *esum;
+};
+
+static LocalWs carve_local(Carver &c, const Plan &p) {
+    LocalWs w;
+    w.e = carve_exact(c, p);
+    w.twiceB = c.take<unsigned long long>(pad64(p.nB));
+    w.esum = c.take<unsigned long long>(pad64(p.m));
+    return w;
 }
 
 }  // namespace bfc
@@ -755,23 +837,11 @@ int bfc_exact_ws_size(const bfc_graph *g, int side, size_t *bytes) {
     return BFC_OK;
 }
 
-static int exact_setup(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes, Plan &p,
-                       ExactWs &w) {
-    if (!d_ws) return BFC_E_NULL;
-    BFC_TRY(make_plan(g, side, &p));
-    if (!aligned256(d_ws)) return BFC_E_ALIGN;
-    if (overflow_risk(p)) return BFC_E_OVERFLOW_RISK;
-    Carver c(d_ws, ws_bytes);
-    w = carve_exact(c, p);
-    if (!c.fits()) return BFC_E_WS_SMALL;
-    return BFC_OK;
-}
-
 int bfc_exact_plan(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes, hipStream_t s) {
     Plan p;
     ExactWs w;
     BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
-    return prepare(p, w, nullptr, 0, s);
+    return prepare(p, w, 0, s);
 }
 
 int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws,
@@ -788,13 +858,12 @@ int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws,
         return BFC_OK;
     }
     CountArgs a;
-    a.offA = p.offA; a.adjA = p.adjA; a.xA = p.xA; a.offB = p.offB; a.adjB = p.adjB;
-    a.seg1 = w.seg1; a.seg_start = w.seg_start; a.seg_win = w.seg_win;
-    a.items = w.items; a.q = w.q; a.nA = p.nA; a.total = tot;
-    int dev = 0;
-    BFC_HIP(hipGetDevice(&dev));
-    unsigned grid = (unsigned)device_cu_count(dev) * 2;
-    k_exact<<<grid, NT, 0, s>>>(a);
+    fill_args(p, w, a);
+    unsigned gn, gw;
+    BFC_TRY(grids(gn, gw));
+    k_exact_narrow<<<gn, WT, 0, s>>>(a);
+    a.total = tot;
+    k_exact_wide<<<gw, NT, 0, s>>>(a);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
@@ -805,27 +874,6 @@ int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws, size_
     BFC_TRY(bfc_exact_plan(g, side, d_ws, ws_bytes, s));
     return bfc_exact_count(g, side, d_total, d_ws, ws_bytes, s);
 }
-
-}  // extern "C"
-
-namespace bfc {
-
-struct LocalWs {
-    ExactWs e;
-    unsigned long long *twiceB, *esum;
-};
-
-static LocalWs carve_local(Carver &c, const Plan &p) {
-    LocalWs w;
-    w.e = carve_exact(c, p);
-    w.twiceB = c.take<unsigned long long>(pad64(p.nB));
-    w.esum = c.take<unsigned long long>(pad64(p.m));
-    return w;
-}
-
-}  // namespace bfc
-
-extern "C" {
 
 int bfc_local_ws_size(const bfc_graph *g, size_t *bytes) {
     if (!bytes) return BFC_E_NULL;
@@ -845,11 +893,7 @@ int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t
     if (!aligned256(d_ws) || ((uintptr_t)d_cnt_l & 7) || ((uintptr_t)d_cnt_r & 7) ||
         ((uintptr_t)d_cnt_e & 7))
         return BFC_E_ALIGN;
-    {
-        Plan q = p;
-        q.wedges = 2 * p.wedges;
-        if (p.wedges >> 63 || overflow_risk(q)) return BFC_E_OVERFLOW_RISK;
-    }
+    if (p.wedges >> 63 || overflow_risk(2 * p.wedges, p.max_deg_A)) return BFC_E_OVERFLOW_RISK;
     Carver c(d_ws, ws_bytes);
     LocalWs w = carve_local(c, p);
     if (!c.fits()) return BFC_E_WS_SMALL;
@@ -860,22 +904,20 @@ int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t
     if (ce) k_zero_u64<<<grid_for(p.m), 256, 0, s>>>(ce, p.m);
     k_zero_u64<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.nB);
     BFC_HIP(hipGetLastError());
-    BFC_TRY(prepare(p, w.e, nullptr, 1, s));
+    BFC_TRY(prepare(p, w.e, 1, s));
     if (p.nA == 0 || p.m == 0) return BFC_OK;
     LocalArgs a;
-    a.c.offA = p.offA; a.c.adjA = p.adjA; a.c.xA = p.xA; a.c.offB = p.offB; a.c.adjB = p.adjB;
-    a.c.seg1 = w.e.seg1; a.c.seg_start = w.e.seg_start; a.c.seg_win = w.e.seg_win;
-    a.c.items = w.e.items; a.c.q = w.e.q; a.c.nA = p.nA; a.c.total = nullptr;
+    fill_args(p, w.e, a.c);
     a.eidA = p.start_r ? g->eid_r : g->eid_l;
     a.idA = p.start_r ? g->id_r : g->id_l;
     a.cntA = p.start_r ? cr : cl;
     a.cntE = ce;
     a.twiceB = w.twiceB;
     a.esum = w.esum;
-    int dev = 0;
-    BFC_HIP(hipGetDevice(&dev));
-    unsigned grid = (unsigned)device_cu_count(dev) * 2;
-    k_local<<<grid, NT, 0, s>>>(a);
+    unsigned gn, gw;
+    BFC_TRY(grids(gn, gw));
+    k_local_narrow<<<gn, WT, 0, s>>>(a);
+    k_local_wide<<<gw, NT, 0, s>>>(a);
     unsigned long long *cntB = p.start_r ? cl : cr;
     if (cntB)
         k_local_finish<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.start_r ? g->id_l : g->id_r,

@@ -219,13 +219,13 @@ struct Layout {
 static Layout carve_storage(Carver &c, uint32_t nl, uint32_t nr, uint64_t m) {
     Layout L;
     L.off_l = c.take<uint32_t>(pad64(nl + 1ull));
-    L.adj_l = c.take<uint32_t>(pad64(m));
+    L.adj_l = c.take<uint32_t>(pad64(m + ADJ_SLACK));
     L.eid_l = c.take<uint32_t>(pad64(m));
     L.xpos_l = c.take<uint32_t>(pad64(m));
     L.rank_l = c.take<uint32_t>(pad64(nl));
     L.id_l = c.take<uint32_t>(pad64(nl));
     L.off_r = c.take<uint32_t>(pad64(nr + 1ull));
-    L.adj_r = c.take<uint32_t>(pad64(m));
+    L.adj_r = c.take<uint32_t>(pad64(m + ADJ_SLACK));
     L.eid_r = c.take<uint32_t>(pad64(m));
     L.xpos_r = c.take<uint32_t>(pad64(m));
     L.rank_r = c.take<uint32_t>(pad64(nr));
