@@ -25,9 +25,9 @@
 // binary search map a piece to its midpoint) and each lane does four 16-byte
 // loads per piece.
 //
-// Wide starts (d_u > 255, few).  A 512-lane workgroup with a 64 KiB table of
-// 32-bit counters (2^14 ranks), midpoints in batches of 256, sub-runs found by
-// binary search.
+// Wide starts (d_u > 255, few).  A 512-lane workgroup shares a 64 KiB table of
+// 32-bit counters (2^14 ranks); each wave walks its own chunks of 64
+// midpoints in the same 16-entry pieces.
 //
 // Scheduling.  Starts are bucketed by their wedge count (log2) and handed out
 // largest first through an atomic queue per class to persistent grids.
@@ -49,7 +49,6 @@ constexpr int WCHUNK = 4;               // starts taken from the queue at once
 
 // wide kernels: 512-lane workgroups
 constexpr int NT = 512;
-constexpr int MIDS = 256;
 constexpr int TBL_WORDS = 1 << G_SHIFT; // 32-bit counters, 64 KiB
 
 struct Plan {
@@ -247,7 +246,13 @@ struct LocalArgs {
     unsigned long long *cntA;     // per start-side vertex (caller ids), or null
     unsigned long long *cntE;     // per edge (caller order), or null
     unsigned long long *twiceB;   // 2 B_v per midpoint rank (workspace)
-    unsigned long long *esum;     // per A-side adjacency position (wide starts)
+};
+
+// Per-midpoint state of wide starts, one slot per A-side adjacency position.
+struct WideScratch {
+    uint32_t *pos, *seg;          // cursor: next position and its segment
+    uint32_t *lo, *hi;            // sub-run of the current window (local counts)
+    unsigned long long *esum;     // sums of final counts (local counts)
 };
 
 // Per-edge and per-midpoint output of one (start, midpoint) pair.
@@ -563,12 +568,23 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
 }
 
 // ------------------------------------------------------------------ wide: workgroup per start
+// Starts with d_u > 255: a workgroup of 8 waves shares a 64 KiB table of
+// 32-bit counters over windows of 2^14 ranks (the segment granularity).  The
+// midpoints are split into chunks of 64; wave w takes chunks w, w + 8, ...
+// and, like the narrow walk, cuts their sub-runs into 16-entry pieces with a
+// wave prefix sum, so a window needs workgroup barriers only at its end.
+// Each midpoint's cursor (position, segment) lives in the workspace at the
+// start's adjacency position; windows no suffix touches are skipped.  LOCAL
+// keeps each midpoint's sub-run of the window to read the final counts back
+// in a second pass.
+constexpr int NWAVES = NT / WT;
+
 struct Shared {
-    uint32_t tbl[TBL_WORDS];
-    uint32_t pre[MIDS], lo[MIDS], hi[MIDS], skip[MIDS];
-    unsigned long long esum[MIDS];
-    uint32_t red[NT / WAVE + 1];
-    unsigned long long red64[NT / WAVE];
+    uint32_t tbl[TBL_WORDS + NT];       // counters, then one zero word per thread
+    uint32_t pre[NWAVES][WT], lo[NWAVES][WT], hi[NWAVES][WT], skip[NWAVES][WT];
+    unsigned long long esum[NWAVES][WT];
+    uint32_t red[NWAVES + 1];
+    unsigned long long red64[NWAVES];
     uint32_t item;
 };
 
@@ -577,84 +593,153 @@ __device__ inline void clear_table(Shared &sh) {
     for (int i = threadIdx.x; i < TBL_WORDS / 4; i += NT) ((uint4 *)sh.tbl)[i] = z;
 }
 
-// Group c of the batch -> midpoint, position and mask (LDS binary search).
-__device__ inline uint32_t locate(const Shared &sh, uint32_t nmid, uint32_t c, uint32_t &base,
-                                  uint32_t &mask) {
-    const uint32_t j = upper_bound_lds(sh.pre, nmid, c) - 1;
-    const uint32_t lo = sh.lo[j];
-    base = ((lo >> 2) + (c - sh.pre[j])) << 2;
-    mask = group_mask(base, lo, sh.hi[j], sh.skip[j]);
-    return j;
+// Order this wave's LDS writes before its later reads (no other wave involved).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
-// One start with d_u > 255: 32-bit counters over windows of 2^14 ranks,
-// midpoints in batches of MIDS, sub-runs found by binary search.  LOCAL runs a
-// second pass per window that sums the final counts per midpoint into
-// esum_g (one slot per A-side adjacency position).
-template <bool LOCAL>
-__device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t u, uint32_t rb,
-                                        uint32_t du, unsigned long long *esum_g) {
-    const uint32_t tid = threadIdx.x;
-    unsigned long long sum = 0;
-    if (LOCAL) {
-        for (uint32_t j = tid; j < du; j += NT) esum_g[rb + j] = 0;
-    } else if (u + 1 >= a.nA) {
-        return 0;
-    }
-    const uint32_t w_first = LOCAL ? 0 : (u + 1) >> G_SHIFT;
-    const uint32_t w_last = (a.nA - 1) >> G_SHIFT;
-    for (uint32_t kw = w_first; kw <= w_last; kw++) {
-        const uint32_t wb = kw << G_SHIFT;
-        const uint32_t we = wb + (1u << G_SHIFT);
-        for (int pass = 0; pass < (LOCAL ? 2 : 1); pass++) {
-            for (uint32_t mb = 0; mb < du; mb += MIDS) {
-                uint32_t lo = 0, hi = 0, nch = 0, skip = INF;
-                if (tid < MIDS && mb + tid < du) {
-                    const uint32_t k = rb + mb + tid;
-                    const uint32_t v = a.adjA[k];
-                    const uint32_t x = a.xA[k];
-                    const uint32_t ev = a.offB[v + 1];
-                    const uint32_t p = LOCAL ? a.offB[v] : x + 1;
-                    if (LOCAL) skip = x;
-                    if (p < ev) {
-                        lo = lower_bound_glb(a.adjB, p, ev, wb);
-                        hi = lower_bound_glb(a.adjB, lo, ev, we);
-                        if (hi > lo) nch = ((hi + 3) >> 2) - (lo >> 2);
-                    }
-                }
-                uint32_t C;
-                const uint32_t ex = block_excl_scan<NT>(nch, sh.red, &C);
-                if (tid < MIDS) {
-                    sh.pre[tid] = ex;
-                    sh.lo[tid] = lo;
-                    sh.hi[tid] = hi;
-                    sh.skip[tid] = skip;
-                    if (LOCAL) sh.esum[tid] = 0;
-                }
-                __syncthreads();
-                const uint32_t nm = du - mb < (uint32_t)MIDS ? du - mb : (uint32_t)MIDS;
-                for (uint32_t c = tid; c < C; c += NT) {
-                    uint32_t base, mask;
-                    const uint32_t j = locate(sh, nm, c, base, mask);
-                    const uint4 g = *(const uint4 *)(a.adjB + base);
-                    const uint32_t w[4] = {g.x, g.y, g.z, g.w};
-                    unsigned long long acc = 0;
+// Piece pi of this wave's chunk (prefix over the chunk's 64 midpoints).
+__device__ inline Piece cpiece(const Shared &sh, uint32_t wv, uint32_t pi, bool valid) {
+    uint32_t j = 0;
 #pragma unroll
-                    for (int i = 0; i < 4; i++) {
-                        if (!(mask >> i & 1)) continue;
-                        if (pass == 0) sum += atomicAdd(&sh.tbl[w[i] - wb], 1u);
-                        else acc += sh.tbl[w[i] - wb];
-                    }
-                    if (LOCAL && pass == 1 && acc) atomicAdd(&sh.esum[j], acc);
+    for (uint32_t s = WT / 2; s; s >>= 1) j = sh.pre[wv][j + s - 1] <= pi ? j + s : j;
+    j = sh.pre[wv][WT - 1] <= pi ? WT : j;
+    j -= 1;
+    Piece pc;
+    const uint32_t lo = sh.lo[wv][j], hi = sh.hi[wv][j];
+    const uint32_t g0 = (lo >> 2) + (pi - sh.pre[wv][j]) * WK;
+    const uint32_t end = min(hi, (g0 + WK) << 2);
+    pc.base = valid ? g0 << 2 : 0;
+    pc.lo = lo;
+    pc.len = valid ? end - lo : 0;
+    pc.skip = sh.skip[wv][j];
+    pc.j = j;
+    return pc;
+}
+
+// pass 0: add one to the counters of the piece's entries, return the sum of
+// previous values; pass 1: return the sum of the final counters.
+__device__ inline uint32_t cpiece_walk(Shared &sh, int pass, const Piece &pc, const uint4 *q,
+                                       uint32_t wb) {
+    const uint32_t zw = TBL_WORDS + threadIdx.x;
+    uint32_t v[4 * WK];
+#pragma unroll
+    for (int k = 0; k < WK; k++) {
+        const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint32_t pos = pc.base + 4 * k + i;
+            const bool on = (pos - pc.lo) < pc.len && pos != pc.skip;
+            const uint32_t idx = on ? w[i] - wb : zw;
+            v[4 * k + i] = pass == 0 ? atomicAdd(&sh.tbl[idx], (uint32_t)on) : sh.tbl[idx];
+        }
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4 * WK; k++) s += v[k];
+    return s;
+}
+
+// One chunk of 64 midpoints (this wave): publish the sub-runs, walk pieces.
+__device__ inline void chunk_walk(const CountArgs &a, Shared &sh, int pass, uint32_t lo,
+                                  uint32_t hi, uint32_t skip, uint32_t wb,
+                                  unsigned long long &sum, unsigned long long &esum_mid) {
+    const uint32_t lane = threadIdx.x & (WT - 1), wv = threadIdx.x / WT;
+    const uint32_t np = hi > lo ? (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK : 0;
+    const uint32_t inc = wave_incl_scan(np);
+    const uint32_t NP = __shfl(inc, WT - 1, WT);
+    sh.pre[wv][lane] = inc - np;
+    sh.lo[wv][lane] = lo;
+    sh.hi[wv][lane] = hi;
+    sh.skip[wv][lane] = skip;
+    if (pass == 1) sh.esum[wv][lane] = 0;
+    wave_sync();
+    const uint32_t rounds = (NP + WT - 1) / WT;
+    uint32_t part = 0;
+    for (uint32_t r = 0; r < rounds; r++) {
+        const uint32_t pi = lane + r * WT;
+        const Piece pc = cpiece(sh, wv, pi < NP ? pi : 0, pi < NP);
+        uint4 q[WK];
+        wfetch<WK>(a.adjB, pc, q);
+        const uint32_t s = cpiece_walk(sh, pass, pc, q, wb);
+        if (pass == 0) part += s;
+        else if (s) atomicAdd(&sh.esum[wv][pc.j], (unsigned long long)s);
+    }
+    sum += part;
+    wave_sync();
+    if (pass == 1) esum_mid = sh.esum[wv][lane];
+    wave_sync();
+}
+
+template <bool LOCAL>
+__device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t rb, uint32_t du,
+                                        const WideScratch &ws) {
+    const uint32_t tid = threadIdx.x, lane = tid & (WT - 1), wv = tid / WT;
+    unsigned long long sum = 0;
+    uint32_t mn = INF;
+    for (uint32_t j = tid; j < du; j += NT) {
+        const uint32_t k = rb + j;
+        const uint32_t v = a.adjA[k];
+        const uint32_t pb = a.offB[v], ev = a.offB[v + 1];
+        uint32_t p = LOCAL ? pb : a.xA[k] + 1, s = 0;
+        if (LOCAL ? (ev - pb > 1) : (p < ev)) {
+            s = a.seg1[p] - 1;
+            mn = min(mn, a.seg_win[s]);
+        } else {
+            p = ev;                             // nothing to walk
+        }
+        ws.pos[k] = p;
+        ws.seg[k] = s;
+        if (LOCAL) ws.esum[k] = 0;
+    }
+    uint32_t kw = block_min<NT>(mn, sh.red);
+    while (kw != INF) {
+        const uint32_t wb = kw << G_SHIFT;
+        uint32_t next = INF;
+        for (uint32_t cb = wv * WT; cb < du; cb += NT) {
+            const uint32_t j = cb + lane, k = rb + j;
+            uint32_t lo = 0, hi = 0, skip = INF;
+            if (j < du) {
+                const uint32_t ev = a.offB[a.adjA[k] + 1];
+                uint32_t p = ws.pos[k], s = ws.seg[k];
+                if (p < ev && a.seg_win[s] == kw) {
+                    lo = p;
+                    const uint32_t e = a.seg_start[s + 1];
+                    hi = e < ev ? e : ev;
+                    p = hi;
+                    s++;
+                    ws.pos[k] = p;
+                    ws.seg[k] = s;
                 }
-                __syncthreads();
-                if (LOCAL && pass == 1 && tid < MIDS && mb + tid < du)
-                    esum_g[rb + mb + tid] += sh.esum[tid];
-                __syncthreads();
+                if (p < ev) next = min(next, a.seg_win[s]);
+                if (LOCAL) {
+                    skip = a.xA[k];
+                    ws.lo[k] = lo;
+                    ws.hi[k] = hi;
+                }
+            }
+            unsigned long long unused;
+            chunk_walk(a, sh, 0, lo, hi, skip, wb, sum, unused);
+        }
+        if (LOCAL) {
+            __syncthreads();                    // all counts of the window are final
+            for (uint32_t cb = wv * WT; cb < du; cb += NT) {
+                const uint32_t j = cb + lane, k = rb + j;
+                uint32_t lo = 0, hi = 0, skip = INF;
+                if (j < du) {
+                    lo = ws.lo[k];
+                    hi = ws.hi[k];
+                    skip = a.xA[k];
+                }
+                unsigned long long e = 0;
+                chunk_walk(a, sh, 1, lo, hi, skip, wb, sum, e);
+                if (j < du && e) ws.esum[k] += e;
             }
         }
-        clear_table(sh);
         __syncthreads();
+        clear_table(sh);
+        kw = block_min<NT>(next, sh.red);
     }
     return sum;
 }
@@ -666,33 +751,36 @@ __device__ inline uint32_t block_take(Shared &sh, QueueState *q) {
     return sh.item;
 }
 
-__global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a) {
+__global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) {
     __shared__ Shared sh;
     clear_table(sh);
+    sh.tbl[TBL_WORDS + threadIdx.x] = 0;
     const uint32_t n = a.q->n_items[1];
     unsigned long long acc = 0;
     for (uint32_t it = block_take(sh, a.q); it < n; it = block_take(sh, a.q)) {
         const uint32_t u = a.items_wide[it];
         const uint32_t rb = a.offA[u];
-        acc += walk_wide<false>(a, sh, u, rb, a.offA[u + 1] - rb, nullptr);
+        acc += walk_wide<false>(a, sh, rb, a.offA[u + 1] - rb, ws);
     }
     acc = block_sum64<NT>(acc, sh.red64);
     finish_launch(a.q, 1, acc, a.total);
 }
 
-__global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a) {
+__global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a, WideScratch ws) {
     __shared__ Shared sh;
     clear_table(sh);
+    sh.tbl[TBL_WORDS + threadIdx.x] = 0;
     const uint32_t n = a.c.q->n_items[1];
     const uint32_t tid = threadIdx.x;
     for (uint32_t it = block_take(sh, a.c.q); it < n; it = block_take(sh, a.c.q)) {
         const uint32_t u = a.c.items_wide[it];
         const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
-        unsigned long long s = walk_wide<true>(a.c, sh, u, rb, du, a.esum);
+        unsigned long long s = walk_wide<true>(a.c, sh, rb, du, ws);
+        __syncthreads();
         for (uint32_t j = tid; j < du; j += NT) {
             const uint32_t k = rb + j;
             const uint32_t v = a.c.adjA[k];
-            emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], a.esum[k]);
+            emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], ws.esum[k]);
         }
         s = block_sum64<NT>(s, sh.red64);
         if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = s;
@@ -710,6 +798,7 @@ __global__ void k_local_finish(const unsigned long long *twiceB, const uint32_t 
 // ------------------------------------------------------------------ host side
 struct ExactWs {
     uint32_t *seg1, *seg_start, *seg_win, *scan_tmp, *items, *items_wide;
+    uint32_t *wpos, *wseg;
     uint8_t *bucket;
     QueueState *q;
 };
@@ -722,6 +811,8 @@ static ExactWs carve_exact(Carver &c, const Plan &p) {
     w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(p.m));
     w.items = c.take<uint32_t>(pad64(p.nA));
     w.items_wide = c.take<uint32_t>(pad64(p.nA));
+    w.wpos = c.take<uint32_t>(pad64(p.m));
+    w.wseg = c.take<uint32_t>(pad64(p.m));
     w.bucket = c.take<uint8_t>(pad64(p.nA));
     w.q = c.take<QueueState>(1);
     return w;
@@ -778,7 +869,7 @@ static int grids(unsigned &narrow, unsigned &wide) {
     BFC_HIP(hipGetDevice(&dev));
     const unsigned cu = (unsigned)device_cu_count(dev);
     narrow = cu * 8;
-    wide = cu;
+    wide = cu * 2;
     return BFC_OK;
 }
 
@@ -797,6 +888,7 @@ static int exact_setup(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes
 struct LocalWs {
     ExactWs e;
     unsigned long long *twiceB, *esum;
+    uint32_t *wlo, *whi;
 };
 
 static LocalWs carve_local(Carver &c, const Plan &p) {
@@ -804,6 +896,8 @@ static LocalWs carve_local(Carver &c, const Plan &p) {
     w.e = carve_exact(c, p);
     w.twiceB = c.take<unsigned long long>(pad64(p.nB));
     w.esum = c.take<unsigned long long>(pad64(p.m));
+    w.wlo = c.take<uint32_t>(pad64(p.m));
+    w.whi = c.take<uint32_t>(pad64(p.m));
     return w;
 }
 
@@ -863,7 +957,8 @@ int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws,
     BFC_TRY(grids(gn, gw));
     k_exact_narrow<<<gn, WT, 0, s>>>(a);
     a.total = tot;
-    k_exact_wide<<<gw, NT, 0, s>>>(a);
+    WideScratch ws = {w.wpos, w.wseg, nullptr, nullptr, nullptr};
+    k_exact_wide<<<gw, NT, 0, s>>>(a, ws);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
@@ -913,11 +1008,11 @@ int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t
     a.cntA = p.start_r ? cr : cl;
     a.cntE = ce;
     a.twiceB = w.twiceB;
-    a.esum = w.esum;
+    WideScratch ws = {w.e.wpos, w.e.wseg, w.wlo, w.whi, w.esum};
     unsigned gn, gw;
     BFC_TRY(grids(gn, gw));
     k_local_narrow<<<gn, WT, 0, s>>>(a);
-    k_local_wide<<<gw, NT, 0, s>>>(a);
+    k_local_wide<<<gw, NT, 0, s>>>(a, ws);
     unsigned long long *cntB = p.start_r ? cl : cr;
     if (cntB)
         k_local_finish<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.start_r ? g->id_l : g->id_r,
