@@ -138,6 +138,60 @@ int bfc_per_vertex(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r,
 int bfc_per_edge(const bfc_graph *g, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes,
                  hipStream_t stream);
 
+/* ---------------------------------------------------------------------- */
+/* Estimators.  Random decisions use Philox-4x32-10 (Salmon et al., SC'11)  */
+/* keyed by `seed`, with one fixed counter per decision, so a result does   */
+/* not depend on thread order and is reproducible bit for bit:             */
+/*   ESpar keep of edge (l, r): counter (l, r, 0x45535052, 0), x = out0 |   */
+/*     out1 << 32, kept iff x < floor(p * 2^64) (p = 1 keeps every edge);   */
+/*   ClrSpar colour of vertex v of side s (0 = L, 1 = R): counter (v, s,    */
+/*     0x434C5253, attempt), x = out0, retried while x >= 2^32 - 2^32 mod N, */
+/*     colour = x mod N;                                                     */
+/*   draw i of VSamp / ESamp: counter (i & 0xffffffff, i >> 32, 0x56445257  */
+/*     / 0x45445257, attempt), x = out0 | out1 << 32, retried while          */
+/*     x >= 2^64 - 2^64 mod n, value x mod n.                                */
+/* Weighted draws (d_probs given) quantise the probabilities to integer     */
+/* weights q_j = p_j > 0 ? max(1, floor(p_j / max(p) * (2^32 - 1))) : 0 and  */
+/* take the first j whose inclusive prefix sum of q exceeds a draw below    */
+/* Q = sum(q).  These calls synchronise the stream (they read sizes or      */
+/* checks back).                                                             */
+/* ---------------------------------------------------------------------- */
+int bfc_spar_ws_size(const bfc_graph *g, size_t *bytes);
+/* ESpar (Sec. 6.1): keep each edge with probability p in (0, 1], count the
+ * kept graph's butterflies beta exactly, estimate = beta / ((p*p)*(p*p)).
+ * *d_kept_bflies = beta, *d_est = estimate (device); *kept_edges (host, may be
+ * NULL) = number of kept edges.  BFC_E_ARG unless 0 < p <= 1. */
+int bfc_espar(const bfc_graph *g, double p, uint64_t seed, uint64_t *d_kept_bflies,
+              double *d_est, uint64_t *kept_edges, void *d_ws, size_t ws_bytes,
+              hipStream_t stream);
+/* ClrSpar (Sec. 6.2): colour the vertices with ncolors >= 1 colours, keep the
+ * monochromatic edges, count their butterflies beta exactly, estimate =
+ * beta * (N * N * N) in binary64.  BFC_E_ARG if ncolors == 0. */
+int bfc_clrspar(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint64_t *d_mono_bflies,
+                double *d_est, uint64_t *kept_edges, void *d_ws, size_t ws_bytes,
+                hipStream_t stream);
+
+/* VSamp (Sec. 5.1): k >= 1 draws with replacement of a vertex, uniformly or
+ * by d_probs (n_left + n_right doubles: L ids then R ids).  d_ids[i] is the
+ * drawn vertex (global id: L id, or n_left + R id), d_counts[i] its count B_v
+ * (vBFC).  *d_est: uniform: (double)sum(counts) * n / (4 k) with the sum exact
+ * in uint64 (the mean of Alg. VSamp over k draws); weighted: the
+ * Hansen-Hurwitz mean of B_v * Q / (4 q_v), summed left to right in blocks of
+ * 1024 draws and the block sums left to right.  BFC_E_PROBS for negative,
+ * NaN, infinite or all-zero probabilities; BFC_E_OVERFLOW_RISK if the uniform
+ * sum overflows. */
+int bfc_vsamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
+int bfc_vsamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
+              uint32_t *d_ids, uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
+              hipStream_t stream);
+/* ESamp (Sec. 5.2): the same over edges (d_probs: n_edges doubles in the
+ * caller's edge order); d_eids[i] the drawn edge's index, d_counts[i] its B_e
+ * (eBFC), estimate with n = n_edges. */
+int bfc_esamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
+int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
+              uint64_t *d_eids, uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
+              hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,17 @@ SIGNATURES = {
                         C.c_void_p], C.c_int),
     "bfc_per_edge": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
                      C.c_int),
+    "bfc_spar_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_espar": ([C.POINTER(bfc_graph), C.c_double, C.c_uint64, C.c_void_p, C.c_void_p,
+                   C.POINTER(C.c_uint64), C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_clrspar": ([C.POINTER(bfc_graph), C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p,
+                     C.POINTER(C.c_uint64), C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_vsamp_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_vsamp": ([C.POINTER(bfc_graph), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
+                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_esamp_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_esamp": ([C.POINTER(bfc_graph), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
+                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
 }
 
 _lib = None

@@ -141,6 +141,62 @@ class Graph:
         u = lambda t, n: t.cpu().numpy().view(np.uint64)[:n].copy() if t is not None else None
         return u(cl, self.n_left), u(cr, self.n_right), u(ce, self.n_edges)
 
+    # -------------------------------------------------------------- estimators
+    def _spar(self, fn, param, seed):
+        L = lib()
+        sz = C.c_size_t()
+        check(L.bfc_spar_ws_size(C.byref(self.g), C.byref(sz)), "spar ws size")
+        ws = _bytes(sz.value, self.device)
+        beta = torch.zeros(1, dtype=torch.int64, device=self.device)
+        est = torch.zeros(1, dtype=torch.float64, device=self.device)
+        kept = C.c_uint64()
+        check(fn(C.byref(self.g), param, seed, C.c_void_p(beta.data_ptr()),
+                 C.c_void_p(est.data_ptr()), C.byref(kept), C.c_void_p(ws.data_ptr()), ws.numel(),
+                 _stream()), "sparsifier")
+        torch.cuda.synchronize(self.device)
+        return int(beta.cpu().numpy().view(np.uint64)[0]), float(est.item()), kept.value
+
+    def espar(self, p, seed):
+        """ESpar: (kept butterflies, estimate, kept edges)."""
+        return self._spar(lib().bfc_espar, C.c_double(p), seed)
+
+    def clrspar(self, ncolors, seed):
+        """ClrSpar: (monochromatic butterflies, estimate, kept edges)."""
+        return self._spar(lib().bfc_clrspar, ncolors, seed)
+
+    def _samp(self, size_fn, fn, n, k, seed, probs, id_dtype):
+        sz = C.c_size_t()
+        check(size_fn(C.byref(self.g), k, C.byref(sz)), "sampler ws size")
+        ws = _bytes(sz.value, self.device)
+        ids = torch.zeros(max(k, 1), dtype=id_dtype, device=self.device)
+        cnt = torch.zeros(max(k, 1), dtype=torch.int64, device=self.device)
+        est = torch.zeros(1, dtype=torch.float64, device=self.device)
+        pp = None
+        if probs is not None:
+            pt = torch.as_tensor(np.ascontiguousarray(probs, dtype=np.float64)).to(self.device)
+            if pt.numel() != n:
+                raise ValueError("probs has the wrong length")
+            pp = C.c_void_p(pt.data_ptr())
+        check(fn(C.byref(self.g), pp, k, seed, C.c_void_p(ids.data_ptr()),
+                 C.c_void_p(cnt.data_ptr()), C.c_void_p(est.data_ptr()), C.c_void_p(ws.data_ptr()),
+                 ws.numel(), _stream()), "sampler")
+        torch.cuda.synchronize(self.device)
+        ids_np = ids.cpu().numpy()
+        ids_np = ids_np.view(np.uint32) if id_dtype == torch.int32 else ids_np.view(np.uint64)
+        return ids_np[:k].copy(), cnt.cpu().numpy().view(np.uint64)[:k].copy(), float(est.item())
+
+    def vsamp(self, k, seed, probs=None):
+        """VSamp: (drawn global ids, their counts, estimate)."""
+        L = lib()
+        return self._samp(L.bfc_vsamp_ws_size, L.bfc_vsamp, self.n_left + self.n_right, k, seed,
+                          probs, torch.int32)
+
+    def esamp(self, k, seed, probs=None):
+        """ESamp: (drawn edge indices, their counts, estimate)."""
+        L = lib()
+        return self._samp(L.bfc_esamp_ws_size, L.bfc_esamp, self.n_edges, k, seed, probs,
+                          torch.int64)
+
     def per_vertex(self):
         cl, cr, _ = self.local(vertices=True, edges=False)
         return cl, cr

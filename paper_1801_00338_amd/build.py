@@ -8,11 +8,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["graph_build.hip", "count.hip"]
+SOURCES = ["graph_build.hip", "count.hip", "estimators.hip"]
 LIB = os.path.join(HERE, "libbfc.so")
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-shared", "-fPIC",
+    # estimates are binary64 in a fixed order: no fused multiply-add contraction
+    "-ffp-contract=off",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),

@@ -126,8 +126,8 @@ struct QueueState {
 // Bucket = bit length of that count (0 = nothing to do); class 1 = wide.
 __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32_t *adjA,
                                               const uint32_t *xA, const uint32_t *offB,
-                                              uint32_t nA, int all_ends, uint8_t *bucket,
-                                              QueueState *q) {
+                                              uint32_t nA, int all_ends, const uint8_t *mark,
+                                              uint8_t *bucket, QueueState *q) {
     __shared__ uint32_t hist[2][NBUCKET];
     for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
     __syncthreads();
@@ -135,6 +135,7 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
     const uint32_t wpb = blockDim.x / WAVE;
     for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < nA; u += gridDim.x * wpb) {
         uint32_t rb = offA[u], re = offA[u + 1];
+        if (mark && !mark[u]) re = rb;          // start not asked for
         unsigned long long t = 0;
         for (uint32_t k = rb + lane; k < re; k += WAVE) {
             uint32_t v = adjA[k];
@@ -246,6 +247,7 @@ struct LocalArgs {
     unsigned long long *cntA;     // per start-side vertex (caller ids), or null
     unsigned long long *cntE;     // per edge (caller order), or null
     unsigned long long *twiceB;   // 2 B_v per midpoint rank (workspace)
+    int pass2;                    // edge / midpoint sums wanted (else B_u only)
 };
 
 // Per-midpoint state of wide starts, one slot per A-side adjacency position.
@@ -399,7 +401,7 @@ __device__ inline void wclear_all(WShared<LOCAL> &sh) {
 // the per-midpoint sums of final counts accumulated in sh.esum.
 template <bool LOCAL>
 __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, uint32_t rb,
-                                        uint32_t du) {
+                                        uint32_t du, bool pass2) {
     const uint32_t lane = threadIdx.x;
     const uint32_t ns = (du + WT - 1) / WT;
     uint32_t p[WSLOTS], ev[WSLOTS], cur[WSLOTS], win[WSLOTS], sn[WSLOTS], w2[WSLOTS], s2[WSLOTS];
@@ -480,7 +482,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             uint4 q[WK];
             wfetch<WK>(a.adjB, pc, q);
             part = wbump(sh, pc, q, wb);
-            if (LOCAL) {
+            if (LOCAL && pass2) {
                 __syncthreads();
                 const uint32_t v = wread(sh, pc, q, wb);
                 if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
@@ -496,7 +498,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
                 wfetch<WK>(a.adjB, pc, q);
                 part += wbump(sh, pc, q, wb);
             }
-            if (LOCAL) {
+            if (LOCAL && pass2) {
                 __syncthreads();
                 for (uint32_t r = 0; r < rounds; r++) {
                     const uint32_t pi = lane + r * WT;
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
         for (uint32_t it = b; it < e; it++) {
             const uint32_t u = a.items[it];
             const uint32_t rb = a.offA[u];
-            acc += wave_walk<false>(a, sh, rb, a.offA[u + 1] - rb);
+            acc += wave_walk<false>(a, sh, rb, a.offA[u + 1] - rb, false);
         }
     }
     acc = wave_sum64(acc);
@@ -553,11 +555,13 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
         for (uint32_t it = b; it < e; it++) {
             const uint32_t u = a.c.items[it];
             const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
-            unsigned long long s = wave_walk<true>(a.c, sh, rb, du);
-            for (uint32_t j = threadIdx.x; j < du; j += WT) {
-                const uint32_t k = rb + j;
-                const uint32_t v = a.c.adjA[k];
-                emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], sh.esum[j]);
+            unsigned long long s = wave_walk<true>(a.c, sh, rb, du, a.pass2);
+            if (a.pass2) {
+                for (uint32_t j = threadIdx.x; j < du; j += WT) {
+                    const uint32_t k = rb + j;
+                    const uint32_t v = a.c.adjA[k];
+                    emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], sh.esum[j]);
+                }
             }
             s = wave_sum64(s);
             if (threadIdx.x == 0 && a.cntA) a.cntA[a.idA[u]] = s;
@@ -674,7 +678,7 @@ __device__ inline void chunk_walk(const CountArgs &a, Shared &sh, int pass, uint
 
 template <bool LOCAL>
 __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t rb, uint32_t du,
-                                        const WideScratch &ws) {
+                                        const WideScratch &ws, bool pass2) {
     const uint32_t tid = threadIdx.x, lane = tid & (WT - 1), wv = tid / WT;
     unsigned long long sum = 0;
     uint32_t mn = INF;
@@ -722,7 +726,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t
             unsigned long long unused;
             chunk_walk(a, sh, 0, lo, hi, skip, wb, sum, unused);
         }
-        if (LOCAL) {
+        if (LOCAL && pass2) {
             __syncthreads();                    // all counts of the window are final
             for (uint32_t cb = wv * WT; cb < du; cb += NT) {
                 const uint32_t j = cb + lane, k = rb + j;
@@ -760,7 +764,7 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
     for (uint32_t it = block_take(sh, a.q); it < n; it = block_take(sh, a.q)) {
         const uint32_t u = a.items_wide[it];
         const uint32_t rb = a.offA[u];
-        acc += walk_wide<false>(a, sh, rb, a.offA[u + 1] - rb, ws);
+        acc += walk_wide<false>(a, sh, rb, a.offA[u + 1] - rb, ws, false);
     }
     acc = block_sum64<NT>(acc, sh.red64);
     finish_launch(a.q, 1, acc, a.total);
@@ -775,12 +779,14 @@ __global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a, WideScratch ws) 
     for (uint32_t it = block_take(sh, a.c.q); it < n; it = block_take(sh, a.c.q)) {
         const uint32_t u = a.c.items_wide[it];
         const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
-        unsigned long long s = walk_wide<true>(a.c, sh, rb, du, ws);
+        unsigned long long s = walk_wide<true>(a.c, sh, rb, du, ws, a.pass2);
         __syncthreads();
-        for (uint32_t j = tid; j < du; j += NT) {
-            const uint32_t k = rb + j;
-            const uint32_t v = a.c.adjA[k];
-            emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], ws.esum[k]);
+        if (a.pass2) {
+            for (uint32_t j = tid; j < du; j += NT) {
+                const uint32_t k = rb + j;
+                const uint32_t v = a.c.adjA[k];
+                emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], ws.esum[k]);
+            }
         }
         s = block_sum64<NT>(s, sh.red64);
         if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = s;
@@ -834,7 +840,7 @@ static bool overflow_risk(uint64_t wedges, uint32_t max_deg) {
 }
 
 // Segments, per-start work buckets and the work queues for one plan.
-static int prepare(const Plan &p, ExactWs &w, int all_ends, hipStream_t s) {
+static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark, hipStream_t s) {
     k_zero_u32<<<1, 256, 0, s>>>((uint32_t *)w.q, (uint64_t)(sizeof(QueueState) / 4));
     if (p.m) {
         k_seg_flags<<<grid_for(p.m), 256, 0, s>>>(p.adjB, p.m, w.seg1);
@@ -847,7 +853,8 @@ static int prepare(const Plan &p, ExactWs &w, int all_ends, hipStream_t s) {
     if (p.nA) {
         unsigned g = grid_for(p.nA, 4);
         if (g > 8192) g = 8192;
-        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.nA, all_ends, w.bucket, w.q);
+        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.nA, all_ends, mark, w.bucket,
+                                 w.q);
         BFC_HIP(hipGetLastError());
     }
     k_bucket_offsets<<<1, 64, 0, s>>>(w.q);
@@ -901,6 +908,69 @@ static LocalWs carve_local(Carver &c, const Plan &p) {
     return w;
 }
 
+// Workspace of bfc_exact for any graph with these sizes (either side).
+size_t exact_ws_bound(uint32_t nl, uint32_t nr, uint64_t m) {
+    Plan p = {};
+    p.nA = nl > nr ? nl : nr;
+    p.nB = p.nA;
+    p.m = m;
+    Carver c(nullptr, 0);
+    carve_exact(c, p);
+    return c.used;
+}
+
+int local_ws_size(const bfc_graph *g, int side, size_t *bytes) {
+    if (!bytes) return BFC_E_NULL;
+    Plan p;
+    BFC_TRY(make_plan(g, side, &p));
+    Carver c(nullptr, 0);
+    carve_local(c, p);
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+// Local counts of the starts on `side` (all, or those whose mark[rank] is
+// set), written into caller-zeroed outputs: B_u of the starts (caller ids),
+// and when asked, B_e of their edges (caller order) and B_v of the midpoints
+// (from the processed starts' edges only).
+int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt_l,
+              uint64_t *d_cnt_r, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes,
+              hipStream_t s) {
+    if (!d_ws || (!d_cnt_l && !d_cnt_r && !d_cnt_e)) return BFC_E_NULL;
+    Plan p;
+    BFC_TRY(make_plan(g, side, &p));
+    if (!aligned256(d_ws)) return BFC_E_ALIGN;
+    if (p.wedges >> 63 || overflow_risk(2 * p.wedges, p.max_deg_A)) return BFC_E_OVERFLOW_RISK;
+    Carver c(d_ws, ws_bytes);
+    LocalWs w = carve_local(c, p);
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    unsigned long long *cl = (unsigned long long *)d_cnt_l, *cr = (unsigned long long *)d_cnt_r,
+                       *ce = (unsigned long long *)d_cnt_e;
+    unsigned long long *cntB = p.start_r ? cl : cr;
+    k_zero_u64<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.nB);
+    BFC_HIP(hipGetLastError());
+    BFC_TRY(prepare(p, w.e, 1, mark, s));
+    if (p.nA == 0 || p.m == 0) return BFC_OK;
+    LocalArgs a;
+    fill_args(p, w.e, a.c);
+    a.eidA = p.start_r ? g->eid_r : g->eid_l;
+    a.idA = p.start_r ? g->id_r : g->id_l;
+    a.cntA = p.start_r ? cr : cl;
+    a.cntE = ce;
+    a.twiceB = w.twiceB;
+    a.pass2 = (ce != nullptr || cntB != nullptr);
+    WideScratch ws = {w.e.wpos, w.e.wseg, w.wlo, w.whi, w.esum};
+    unsigned gn, gw;
+    BFC_TRY(grids(gn, gw));
+    k_local_narrow<<<gn, WT, 0, s>>>(a);
+    k_local_wide<<<gw, NT, 0, s>>>(a, ws);
+    if (cntB)
+        k_local_finish<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.start_r ? g->id_l : g->id_r,
+                                                       p.nB, cntB);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
 }  // namespace bfc
 
 using namespace bfc;
@@ -935,7 +1005,7 @@ int bfc_exact_plan(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes, hi
     Plan p;
     ExactWs w;
     BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
-    return prepare(p, w, 0, s);
+    return prepare(p, w, 0, nullptr, s);
 }
 
 int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws,
@@ -971,54 +1041,21 @@ int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws, size_
 }
 
 int bfc_local_ws_size(const bfc_graph *g, size_t *bytes) {
-    if (!bytes) return BFC_E_NULL;
-    Plan p;
-    BFC_TRY(make_plan(g, BFC_SIDE_AUTO, &p));
-    Carver c(nullptr, 0);
-    carve_local(c, p);
-    *bytes = c.used;
-    return BFC_OK;
+    return bfc::local_ws_size(g, BFC_SIDE_AUTO, bytes);
 }
 
 int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t *d_cnt_e,
               void *d_ws, size_t ws_bytes, hipStream_t s) {
-    if (!d_ws || (!d_cnt_l && !d_cnt_r && !d_cnt_e)) return BFC_E_NULL;
-    Plan p;
-    BFC_TRY(make_plan(g, BFC_SIDE_AUTO, &p));
-    if (!aligned256(d_ws) || ((uintptr_t)d_cnt_l & 7) || ((uintptr_t)d_cnt_r & 7) ||
-        ((uintptr_t)d_cnt_e & 7))
+    if (!g || !d_ws || (!d_cnt_l && !d_cnt_r && !d_cnt_e)) return BFC_E_NULL;
+    if (((uintptr_t)d_cnt_l & 7) || ((uintptr_t)d_cnt_r & 7) || ((uintptr_t)d_cnt_e & 7))
         return BFC_E_ALIGN;
-    if (p.wedges >> 63 || overflow_risk(2 * p.wedges, p.max_deg_A)) return BFC_E_OVERFLOW_RISK;
-    Carver c(d_ws, ws_bytes);
-    LocalWs w = carve_local(c, p);
-    if (!c.fits()) return BFC_E_WS_SMALL;
     unsigned long long *cl = (unsigned long long *)d_cnt_l, *cr = (unsigned long long *)d_cnt_r,
                        *ce = (unsigned long long *)d_cnt_e;
     if (cl) k_zero_u64<<<grid_for(g->n_left), 256, 0, s>>>(cl, g->n_left);
     if (cr) k_zero_u64<<<grid_for(g->n_right), 256, 0, s>>>(cr, g->n_right);
-    if (ce) k_zero_u64<<<grid_for(p.m), 256, 0, s>>>(ce, p.m);
-    k_zero_u64<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.nB);
+    if (ce) k_zero_u64<<<grid_for(g->n_edges), 256, 0, s>>>(ce, g->n_edges);
     BFC_HIP(hipGetLastError());
-    BFC_TRY(prepare(p, w.e, 1, s));
-    if (p.nA == 0 || p.m == 0) return BFC_OK;
-    LocalArgs a;
-    fill_args(p, w.e, a.c);
-    a.eidA = p.start_r ? g->eid_r : g->eid_l;
-    a.idA = p.start_r ? g->id_r : g->id_l;
-    a.cntA = p.start_r ? cr : cl;
-    a.cntE = ce;
-    a.twiceB = w.twiceB;
-    WideScratch ws = {w.e.wpos, w.e.wseg, w.wlo, w.whi, w.esum};
-    unsigned gn, gw;
-    BFC_TRY(grids(gn, gw));
-    k_local_narrow<<<gn, WT, 0, s>>>(a);
-    k_local_wide<<<gw, NT, 0, s>>>(a, ws);
-    unsigned long long *cntB = p.start_r ? cl : cr;
-    if (cntB)
-        k_local_finish<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.start_r ? g->id_l : g->id_r,
-                                                       p.nB, cntB);
-    BFC_HIP(hipGetLastError());
-    return BFC_OK;
+    return bfc::local_run(g, BFC_SIDE_AUTO, nullptr, d_cnt_l, d_cnt_r, d_cnt_e, d_ws, ws_bytes, s);
 }
 
 int bfc_per_vertex(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, void *d_ws,

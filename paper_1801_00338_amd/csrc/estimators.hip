@@ -1,0 +1,657 @@
+// Estimators built on the exact and local counts (Sec. 5 and 6 of the paper):
+// edge sparsification (ESpar), colourful sparsification (ClrSpar), vertex
+// sampling (VSamp) and edge sampling (ESamp).
+//
+// Random decisions come from Philox-4x32-10 (Salmon, Moraes, Dror, Shaw,
+// SC'11) keyed by the 64-bit seed (key = seed low word, seed high word); each
+// decision has a fixed counter, so results do not depend on thread order:
+//   ESpar keep of edge (l, r):   counter (l, r, 'ESPR', 0), x = out0 | out1 << 32,
+//                                kept iff x < floor(p * 2^64)  (p = 1 keeps all)
+//   ClrSpar colour of vertex v of side s (0 = L, 1 = R):
+//                                counter (v, s, 'CLRS', attempt), x = out0,
+//                                rejected while x >= 2^32 - 2^32 mod N, colour x mod N
+//   draw i of VSamp / ESamp:     counter (i lo, i hi, 'VDRW' / 'EDRW', attempt),
+//                                x = out0 | out1 << 32, rejected while
+//                                x >= 2^64 - 2^64 mod n, value x mod n
+// Weighted draws quantise probabilities to integer weights
+// q_j = prob_j > 0 ? max(1, floor(prob_j / max(prob) * (2^32 - 1))) : 0 and
+// pick the first j whose inclusive prefix sum of q exceeds a uniform draw
+// below the total Q.
+#include "common.h"
+
+namespace bfc {
+
+constexpr uint32_t TAG_ESPAR = 0x45535052u;
+constexpr uint32_t TAG_COLOR = 0x434C5253u;
+constexpr uint32_t TAG_VDRAW = 0x56445257u;
+constexpr uint32_t TAG_EDRAW = 0x45445257u;
+constexpr uint32_t COMBINE_BLOCK = 1024;   // draws summed left to right per block
+
+// ------------------------------------------------------------------ Philox
+__device__ inline void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed,
+                              uint32_t out[4]) {
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// Uniform value below n (n >= 1) by rejection.
+__device__ inline uint64_t draw_below(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag,
+                                      uint64_t n) {
+    const uint64_t rem = (0 - n) % n;         // 2^64 mod n
+    uint32_t o[4];
+    for (uint32_t attempt = 0;; attempt++) {
+        philox(a, b, tag, attempt, seed, o);
+        const uint64_t x = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+        if (rem == 0 || x < 0 - rem) return x % n;
+    }
+}
+
+__device__ inline uint32_t colour_of(uint64_t seed, uint32_t side, uint32_t v, uint32_t N) {
+    const uint64_t lim = (0x100000000ull / N) * N;
+    uint32_t o[4];
+    for (uint32_t attempt = 0;; attempt++) {
+        philox(v, side, TAG_COLOR, attempt, seed, o);
+        if ((uint64_t)o[0] < lim) return o[0] % N;
+    }
+}
+
+// ------------------------------------------------------------------ sparsifier kernels
+// Every L row, one wave per row: the keep flag of each edge (l, r) by ids.
+struct FilterArgs {
+    const uint32_t *off_l, *adj_l, *id_l, *id_r;
+    uint32_t nl;
+    int kind;                   // 0 = ESpar, 1 = ClrSpar
+    uint64_t seed, thresh;      // ESpar: keep iff x < thresh (keep_all overrides)
+    int keep_all;
+    const uint32_t *col_l, *col_r;  // ClrSpar colours by id
+};
+
+__device__ inline uint32_t keep_edge(const FilterArgs &f, uint32_t l, uint32_t r) {
+    if (f.keep_all) return 1u;
+    if (f.kind == 0) {
+        uint32_t o[4];
+        philox(l, r, TAG_ESPAR, 0, f.seed, o);
+        const uint64_t x = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+        return x < f.thresh;
+    }
+    return f.col_l[l] == f.col_r[r];
+}
+
+__global__ __launch_bounds__(256) void k_filter(FilterArgs f, uint32_t *flag) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
+    for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < f.nl; u += gridDim.x * wpb) {
+        const uint32_t l = f.id_l[u];
+        for (uint32_t k = f.off_l[u] + lane; k < f.off_l[u + 1]; k += WAVE)
+            flag[k] = keep_edge(f, l, f.id_r[f.adj_l[k]]);
+    }
+}
+
+// Kept edges, compacted by the inclusive scan of the flags (same row walk).
+__global__ __launch_bounds__(256) void k_compact(FilterArgs f, const uint32_t *scan1,
+                                                 uint32_t *kl, uint32_t *kr) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
+    for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < f.nl; u += gridDim.x * wpb) {
+        const uint32_t l = f.id_l[u];
+        for (uint32_t k = f.off_l[u] + lane; k < f.off_l[u + 1]; k += WAVE) {
+            const uint32_t prev = k ? scan1[k - 1] : 0;
+            if (scan1[k] != prev) {
+                kl[prev] = l;
+                kr[prev] = f.id_r[f.adj_l[k]];
+            }
+        }
+    }
+}
+
+__global__ void k_colours(uint32_t n, uint32_t side, uint32_t N, uint64_t seed, uint32_t *col) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        col[v] = colour_of(seed, side, v, N);
+}
+
+__global__ void k_est_scale(const unsigned long long *beta, double scale_div, double scale_mul,
+                            double *est) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double b = (double)*beta;
+        *est = scale_div != 0.0 ? b / scale_div : b * scale_mul;
+    }
+}
+
+// ------------------------------------------------------------------ sampler kernels
+struct ProbFlags {
+    unsigned long long max_bits;   // bit pattern of the largest probability (all >= 0)
+    uint32_t bad;                  // some probability is negative, NaN or infinite
+    uint32_t overflow;             // the uniform combine's sum overflowed
+};
+
+__global__ void k_prob_scan(const double *probs, uint64_t n, ProbFlags *f) {
+    unsigned long long mx = 0;
+    uint32_t bad = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double p = probs[i];
+        if (!(p >= 0.0) || isinf(p)) bad = 1;
+        else if (p > 0.0) mx = max(mx, (unsigned long long)__double_as_longlong(p));
+    }
+    if (bad) atomicOr(&f->bad, 1u);
+    if (mx) atomicMax(&f->max_bits, mx);
+}
+
+__global__ void k_quantise(const double *probs, uint64_t n, const ProbFlags *f,
+                           unsigned long long *w) {
+    const double mx = __longlong_as_double((long long)f->max_bits);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double p = probs[i];
+        unsigned long long q = 0;
+        if (p > 0.0) {
+            const double s = floor(p / mx * 4294967295.0);
+            const uint32_t v = (uint32_t)s;
+            q = v < 1 ? 1 : v;
+        }
+        w[i] = q;
+    }
+}
+
+// Inclusive prefix sum of uint64 (same reduce-then-scan as the uint32 scan).
+constexpr int S64_NT = 256, S64_PER = 8, S64_TILE = S64_NT * S64_PER;
+
+__global__ __launch_bounds__(S64_NT) void k_s64_tile(const unsigned long long *in, uint64_t n,
+                                                     unsigned long long *sums) {
+    __shared__ unsigned long long red[S64_NT / WAVE];
+    const uint64_t base = (uint64_t)blockIdx.x * S64_TILE;
+    unsigned long long s = 0;
+    for (int i = 0; i < S64_PER; i++) {
+        const uint64_t idx = base + (uint64_t)i * S64_NT + threadIdx.x;
+        if (idx < n) s += in[idx];
+    }
+    s = block_sum64<S64_NT>(s, red);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ void k_s64_sums(unsigned long long *sums, uint32_t nt) {
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        for (uint32_t i = 0; i < nt; i++) {
+            const unsigned long long v = sums[i];
+            sums[i] = run;
+            run += v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(S64_NT) void k_s64_apply(unsigned long long *io, uint64_t n,
+                                                      const unsigned long long *offs) {
+    __shared__ unsigned long long wsum[S64_NT / WAVE];
+    const uint64_t base = (uint64_t)blockIdx.x * S64_TILE + (uint64_t)threadIdx.x * S64_PER;
+    unsigned long long v[S64_PER], s = 0;
+#pragma unroll
+    for (int i = 0; i < S64_PER; i++) {
+        v[i] = base + i < n ? io[base + i] : 0;
+        s += v[i];
+    }
+    // exclusive scan of the per-thread sums across the block
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    unsigned long long inc = s;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        unsigned long long t = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += t;
+    }
+    if (lane == WAVE - 1) wsum[wid] = inc;
+    __syncthreads();
+    unsigned long long run = offs[blockIdx.x] + inc - s;
+    for (int w = 0; w < wid; w++) run += wsum[w];
+#pragma unroll
+    for (int i = 0; i < S64_PER; i++) {
+        run += v[i];
+        if (base + i < n) io[base + i] = run;
+    }
+}
+
+static int scan_u64_inclusive(unsigned long long *io, uint64_t n, unsigned long long *tmp,
+                              hipStream_t s) {
+    if (n == 0) return BFC_OK;
+    const uint32_t nt = (uint32_t)((n + S64_TILE - 1) / S64_TILE);
+    k_s64_tile<<<nt, S64_NT, 0, s>>>(io, n, tmp);
+    k_s64_sums<<<1, 64, 0, s>>>(tmp, nt);
+    k_s64_apply<<<nt, S64_NT, 0, s>>>(io, n, tmp);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+// Draw i: an index below n (uniform) or by weight (prefix sums `pre`, total
+// in pre[n-1]); its weight goes to wdraw for the estimate.
+__global__ void k_draw(uint64_t k, uint64_t n, uint64_t seed, uint32_t tag,
+                       const unsigned long long *pre, const unsigned long long *w,
+                       unsigned long long *out, uint32_t *wdraw) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < k;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t j;
+        if (pre) {
+            const uint64_t t = draw_below(seed, (uint32_t)i, (uint32_t)(i >> 32), tag, pre[n - 1]);
+            uint64_t lo = 0, hi = n;          // first j with pre[j] > t
+            while (lo < hi) {
+                const uint64_t mid = lo + (hi - lo) / 2;
+                if (pre[mid] > t) hi = mid; else lo = mid + 1;
+            }
+            j = lo;
+            wdraw[i] = (uint32_t)w[j];
+        } else {
+            j = draw_below(seed, (uint32_t)i, (uint32_t)(i >> 32), tag, n);
+        }
+        out[i] = j;
+    }
+}
+
+// VSamp: mark the drawn vertices by rank on their side.
+__global__ void k_mark_vertices(uint64_t k, const unsigned long long *draw, uint32_t nl,
+                                const uint32_t *rank_l, const uint32_t *rank_r, uint8_t *mark_l,
+                                uint8_t *mark_r, uint32_t *ids) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < k;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t id = (uint32_t)draw[i];
+        ids[i] = id;
+        if (id < nl) mark_l[rank_l[id]] = 1;
+        else mark_r[rank_r[id - nl]] = 1;
+    }
+}
+
+__global__ void k_gather_vertex(uint64_t k, const uint32_t *ids, uint32_t nl,
+                                const unsigned long long *cl, const unsigned long long *cr,
+                                unsigned long long *counts) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < k;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t id = ids[i];
+        counts[i] = id < nl ? cl[id] : cr[id - nl];
+    }
+}
+
+// ESamp: A-side CSR position of every edge, then mark the drawn edges' starts.
+__global__ void k_pos_of_edge(const uint32_t *eidA, uint64_t m, uint32_t *pos) {
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < m;
+         k += (uint64_t)gridDim.x * blockDim.x)
+        pos[eidA[k]] = (uint32_t)k;
+}
+
+__global__ void k_mark_edges(uint64_t k, const unsigned long long *draw, const uint32_t *pos,
+                             const uint32_t *offA, uint32_t nA, uint8_t *mark) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < k;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = pos[draw[i]];
+        uint32_t lo = 0, hi = nA;             // row u with offA[u] <= p < offA[u+1]
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (offA[mid + 1] > p) hi = mid; else lo = mid + 1;
+        }
+        mark[lo] = 1;
+    }
+}
+
+__global__ void k_gather_edge(uint64_t k, const unsigned long long *draw,
+                              const unsigned long long *ce, unsigned long long *counts,
+                              unsigned long long *eids) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < k;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        eids[i] = draw[i];
+        counts[i] = ce[draw[i]];
+    }
+}
+
+// Estimate of a sampler.  Uniform: sum of counts (exact, uint64) * n /
+// (4 k).  Weighted: term_i = count_i * (Q / (4 q_i)) summed left to right
+// within blocks of COMBINE_BLOCK draws, block sums left to right, over k.
+__global__ __launch_bounds__(256) void k_combine(uint64_t k, uint64_t n,
+                                                 const unsigned long long *counts,
+                                                 const uint32_t *wdraw,
+                                                 const unsigned long long *pre,
+                                                 double *parts, ProbFlags *f, double *est) {
+    __shared__ int ovf;
+    if (threadIdx.x == 0) ovf = 0;
+    __syncthreads();
+    const uint64_t nb = (k + COMBINE_BLOCK - 1) / COMBINE_BLOCK;
+    if (pre) {
+        const double Q = (double)pre[n - 1];
+        for (uint64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+            double part = 0.0;
+            const uint64_t e = min((uint64_t)(b + 1) * COMBINE_BLOCK, k);
+            for (uint64_t i = b * COMBINE_BLOCK; i < e; i++)
+                part += (double)counts[i] * (Q / (4.0 * (double)wdraw[i]));
+            parts[b] = part;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double total = 0.0;
+            for (uint64_t b = 0; b < nb; b++) total += parts[b];
+            *est = total / (double)k;
+        }
+    } else {
+        // exact uint64 sums per thread, then in thread order
+        unsigned long long s = 0;
+        for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) {
+            const unsigned long long c = counts[i];
+            if (s + c < s) ovf = 1;
+            s += c;
+        }
+        ((unsigned long long *)parts)[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (unsigned i = 0; i < blockDim.x; i++) {
+                const unsigned long long c = ((unsigned long long *)parts)[i];
+                if (t + c < t) ovf = 1;
+                t += c;
+            }
+            *est = ((double)t * (double)n) / (4.0 * (double)k);
+            if (ovf) f->overflow = 1;
+        }
+    }
+}
+
+static inline unsigned grid_for(uint64_t n, int nt = 256) {
+    uint64_t g = (n + nt - 1) / nt;
+    if (g < 1) g = 1;
+    if (g > 65535ull * 16) g = 65535ull * 16;
+    return (unsigned)g;
+}
+
+// ------------------------------------------------------------------ host: sparsifiers
+struct SparWs {
+    uint32_t *flag, *scan_tmp, *kl, *kr, *col_l, *col_r;
+    void *storage;
+    size_t storage_bytes;
+    void *work;                 // graph build workspace, then the exact count's
+    size_t work_bytes;
+};
+
+static int carve_spar(Carver &c, uint32_t nl, uint32_t nr, uint64_t m, SparWs &w) {
+    size_t sb, bb;
+    BFC_TRY(bfc_graph_storage_size(nl, nr, m, &sb));
+    BFC_TRY(bfc_graph_build_ws_size(nl, nr, m, &bb));
+    const size_t eb = exact_ws_bound(nl, nr, m);
+    w.flag = c.take<uint32_t>(pad64(m));
+    w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(m));
+    w.kl = c.take<uint32_t>(pad64(m));
+    w.kr = c.take<uint32_t>(pad64(m));
+    w.col_l = c.take<uint32_t>(pad64(nl));
+    w.col_r = c.take<uint32_t>(pad64(nr));
+    w.storage_bytes = sb;
+    w.storage = c.take<char>(sb);
+    w.work_bytes = bb > eb ? bb : eb;
+    w.work = c.take<char>(w.work_bytes);
+    return BFC_OK;
+}
+
+// Filter, compact, rebuild and count the kept graph.
+static int sparsify_count(const bfc_graph *g, FilterArgs f, SparWs &w, uint64_t *d_beta,
+                          uint64_t *kept, hipStream_t s) {
+    const uint64_t m = g->n_edges;
+    uint64_t mk = 0;
+    if (m) {
+        unsigned gr = grid_for(g->n_left, 4);
+        if (gr > 8192) gr = 8192;
+        k_filter<<<gr, 256, 0, s>>>(f, w.flag);
+        BFC_HIP(hipGetLastError());
+        BFC_TRY(scan_u32_inclusive(w.flag, w.flag, m, w.scan_tmp, s));
+        k_compact<<<gr, 256, 0, s>>>(f, w.flag, w.kl, w.kr);
+        BFC_HIP(hipGetLastError());
+        uint32_t last = 0;
+        BFC_HIP(hipMemcpyAsync(&last, w.flag + (m - 1), 4, hipMemcpyDeviceToHost, s));
+        BFC_HIP(hipStreamSynchronize(s));
+        mk = last;
+    }
+    if (kept) *kept = mk;
+    bfc_graph h;
+    BFC_TRY(bfc_graph_build(g->n_left, g->n_right, mk, w.kl, w.kr, w.storage, w.storage_bytes,
+                            w.work, w.work_bytes, s, &h));
+    return bfc_exact(&h, BFC_SIDE_AUTO, d_beta, w.work, w.work_bytes, s);
+}
+
+}  // namespace bfc
+
+using namespace bfc;
+
+extern "C" {
+
+int bfc_spar_ws_size(const bfc_graph *g, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    Carver c(nullptr, 0);
+    SparWs w;
+    BFC_TRY(carve_spar(c, g->n_left, g->n_right, g->n_edges, w));
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_espar(const bfc_graph *g, double p, uint64_t seed, uint64_t *d_beta, double *d_est,
+              uint64_t *kept_edges, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!g || !d_beta || !d_est || !d_ws) return BFC_E_NULL;
+    if (!(p > 0.0) || !(p <= 1.0)) return BFC_E_ARG;
+    if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    SparWs w;
+    BFC_TRY(carve_spar(c, g->n_left, g->n_right, g->n_edges, w));
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    FilterArgs f = {};
+    f.off_l = g->off_l; f.adj_l = g->adj_l; f.id_l = g->id_l; f.id_r = g->id_r;
+    f.nl = g->n_left;
+    f.kind = 0;
+    f.seed = seed;
+    f.keep_all = p >= 1.0;
+    f.thresh = f.keep_all ? 0 : (uint64_t)ldexp(p, 64);
+    BFC_TRY(sparsify_count(g, f, w, d_beta, kept_edges, s));
+    k_est_scale<<<1, 64, 0, s>>>((unsigned long long *)d_beta, (p * p) * (p * p), 0.0, d_est);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+int bfc_clrspar(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint64_t *d_beta,
+                double *d_est, uint64_t *kept_edges, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!g || !d_beta || !d_est || !d_ws) return BFC_E_NULL;
+    if (ncolors == 0) return BFC_E_ARG;
+    if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    SparWs w;
+    BFC_TRY(carve_spar(c, g->n_left, g->n_right, g->n_edges, w));
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    FilterArgs f = {};
+    f.off_l = g->off_l; f.adj_l = g->adj_l; f.id_l = g->id_l; f.id_r = g->id_r;
+    f.nl = g->n_left;
+    f.kind = 1;
+    f.seed = seed;
+    f.keep_all = ncolors == 1;
+    f.col_l = w.col_l;
+    f.col_r = w.col_r;
+    if (!f.keep_all) {
+        if (g->n_left) k_colours<<<grid_for(g->n_left), 256, 0, s>>>(g->n_left, 0, ncolors, seed, w.col_l);
+        if (g->n_right) k_colours<<<grid_for(g->n_right), 256, 0, s>>>(g->n_right, 1, ncolors, seed, w.col_r);
+        BFC_HIP(hipGetLastError());
+    }
+    BFC_TRY(sparsify_count(g, f, w, d_beta, kept_edges, s));
+    const double N = (double)ncolors;
+    k_est_scale<<<1, 64, 0, s>>>((unsigned long long *)d_beta, 0.0, N * N * N, d_est);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ host: samplers
+namespace bfc {
+
+struct SampWs {
+    ProbFlags *flags;
+    unsigned long long *w, *pre, *scan_tmp, *draw, *cnt_l, *cnt_r, *cnt_e;
+    uint32_t *wdraw, *pos;
+    uint8_t *mark_l, *mark_r;
+    double *parts;
+    void *local;
+    size_t local_bytes;
+};
+
+static int carve_samp(Carver &c, const bfc_graph *g, uint64_t n, uint64_t k, int edges,
+                      SampWs &w) {
+    size_t lb = 0, t;
+    BFC_TRY(local_ws_size(g, BFC_SIDE_L, &t));
+    lb = t;
+    BFC_TRY(local_ws_size(g, BFC_SIDE_R, &t));
+    lb = t > lb ? t : lb;
+    w.flags = c.take<ProbFlags>(1);
+    w.w = c.take<unsigned long long>(pad64(n));
+    w.pre = c.take<unsigned long long>(pad64(n));
+    w.scan_tmp = c.take<unsigned long long>((n + S64_TILE - 1) / S64_TILE + 64);
+    w.draw = c.take<unsigned long long>(pad64(k));
+    w.wdraw = c.take<uint32_t>(pad64(k));
+    w.parts = c.take<double>((k + COMBINE_BLOCK - 1) / COMBINE_BLOCK + 1024);
+    w.mark_l = c.take<uint8_t>(pad64(g->n_left));
+    w.mark_r = c.take<uint8_t>(pad64(g->n_right));
+    if (edges) {
+        w.cnt_e = c.take<unsigned long long>(pad64(g->n_edges));
+        w.pos = c.take<uint32_t>(pad64(g->n_edges));
+        w.cnt_l = w.cnt_r = nullptr;
+    } else {
+        w.cnt_l = c.take<unsigned long long>(pad64(g->n_left));
+        w.cnt_r = c.take<unsigned long long>(pad64(g->n_right));
+        w.cnt_e = nullptr;
+        w.pos = nullptr;
+    }
+    w.local_bytes = lb;
+    w.local = c.take<char>(lb);
+    return BFC_OK;
+}
+
+// Weights, prefix sums and k draws over n items; returns BFC_E_PROBS for
+// invalid probabilities (reads the check back: synchronises).
+static int sample_draws(const double *d_probs, uint64_t n, uint64_t k, uint64_t seed,
+                        uint32_t tag, SampWs &w, hipStream_t s) {
+    BFC_HIP(hipMemsetAsync(w.flags, 0, sizeof(ProbFlags), s));
+    if (d_probs) {
+        k_prob_scan<<<grid_for(n), 256, 0, s>>>(d_probs, n, w.flags);
+        ProbFlags hf;
+        BFC_HIP(hipMemcpyAsync(&hf, w.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+        BFC_HIP(hipStreamSynchronize(s));
+        if (hf.bad || hf.max_bits == 0) return BFC_E_PROBS;
+        k_quantise<<<grid_for(n), 256, 0, s>>>(d_probs, n, w.flags, w.w);
+        BFC_HIP(hipMemcpyAsync(w.pre, w.w, n * sizeof(unsigned long long),
+                               hipMemcpyDeviceToDevice, s));
+        BFC_TRY(scan_u64_inclusive(w.pre, n, w.scan_tmp, s));
+    }
+    k_draw<<<grid_for(k), 256, 0, s>>>(k, n, seed, tag, d_probs ? w.pre : nullptr, w.w, w.draw,
+                                       w.wdraw);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+static int finish_estimate(uint64_t k, uint64_t n, const unsigned long long *counts, bool weighted,
+                           SampWs &w, double *d_est, hipStream_t s) {
+    k_combine<<<1, 256, 0, s>>>(k, n, counts, w.wdraw, weighted ? w.pre : nullptr, w.parts,
+                                w.flags, d_est);
+    BFC_HIP(hipGetLastError());
+    ProbFlags hf;
+    BFC_HIP(hipMemcpyAsync(&hf, w.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipStreamSynchronize(s));
+    return hf.overflow ? BFC_E_OVERFLOW_RISK : BFC_OK;
+}
+
+}  // namespace bfc
+
+extern "C" {
+
+int bfc_vsamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    Carver c(nullptr, 0);
+    SampWs w;
+    BFC_TRY(carve_samp(c, g, (uint64_t)g->n_left + g->n_right, k, 0, w));
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_vsamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
+              uint32_t *d_ids, uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
+              hipStream_t s) {
+    if (!g || !d_ids || !d_counts || !d_est || !d_ws) return BFC_E_NULL;
+    const uint64_t n = (uint64_t)g->n_left + g->n_right;
+    if (k == 0 || n == 0) return BFC_E_ARG;
+    if (!aligned256(d_ws) || ((uintptr_t)d_counts & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    SampWs w;
+    BFC_TRY(carve_samp(c, g, n, k, 0, w));
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    BFC_TRY(sample_draws(d_probs, n, k, seed, TAG_VDRAW, w, s));
+    BFC_HIP(hipMemsetAsync(w.mark_l, 0, pad64(g->n_left), s));
+    BFC_HIP(hipMemsetAsync(w.mark_r, 0, pad64(g->n_right), s));
+    k_mark_vertices<<<grid_for(k), 256, 0, s>>>(k, w.draw, g->n_left, g->rank_l, g->rank_r,
+                                                w.mark_l, w.mark_r, d_ids);
+    BFC_HIP(hipMemsetAsync(w.cnt_l, 0, pad64(g->n_left) * 8, s));
+    BFC_HIP(hipMemsetAsync(w.cnt_r, 0, pad64(g->n_right) * 8, s));
+    BFC_HIP(hipGetLastError());
+    // vBFC of every drawn vertex: the local walk from each side over the
+    // marked starts only, per-vertex counts only
+    if (g->n_left)
+        BFC_TRY(local_run(g, BFC_SIDE_L, w.mark_l, (uint64_t *)w.cnt_l, nullptr, nullptr, w.local,
+                          w.local_bytes, s));
+    if (g->n_right)
+        BFC_TRY(local_run(g, BFC_SIDE_R, w.mark_r, nullptr, (uint64_t *)w.cnt_r, nullptr, w.local,
+                          w.local_bytes, s));
+    k_gather_vertex<<<grid_for(k), 256, 0, s>>>(k, d_ids, g->n_left, w.cnt_l, w.cnt_r,
+                                                (unsigned long long *)d_counts);
+    BFC_HIP(hipGetLastError());
+    return finish_estimate(k, n, (unsigned long long *)d_counts, d_probs != nullptr, w, d_est, s);
+}
+
+int bfc_esamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    Carver c(nullptr, 0);
+    SampWs w;
+    BFC_TRY(carve_samp(c, g, g->n_edges, k, 1, w));
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
+              uint64_t *d_eids, uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
+              hipStream_t s) {
+    if (!g || !d_eids || !d_counts || !d_est || !d_ws) return BFC_E_NULL;
+    const uint64_t m = g->n_edges;
+    if (k == 0 || m == 0) return BFC_E_ARG;
+    if (!aligned256(d_ws) || ((uintptr_t)d_counts & 7) || ((uintptr_t)d_eids & 7) ||
+        ((uintptr_t)d_est & 7))
+        return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    SampWs w;
+    BFC_TRY(carve_samp(c, g, m, k, 1, w));
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    BFC_TRY(sample_draws(d_probs, m, k, seed, TAG_EDRAW, w, s));
+    // eBFC of every drawn edge: walk from the side the paper's rule picks,
+    // over the starts of the drawn edges, per-edge counts
+    const int side = bfc_side_used(g, BFC_SIDE_AUTO);
+    const bool from_r = side == BFC_SIDE_R;
+    const uint32_t nA = from_r ? g->n_right : g->n_left;
+    uint8_t *mark = from_r ? w.mark_r : w.mark_l;
+    BFC_HIP(hipMemsetAsync(mark, 0, pad64(nA), s));
+    k_pos_of_edge<<<grid_for(m), 256, 0, s>>>(from_r ? g->eid_r : g->eid_l, m, w.pos);
+    k_mark_edges<<<grid_for(k), 256, 0, s>>>(k, w.draw, w.pos, from_r ? g->off_r : g->off_l, nA,
+                                             mark);
+    BFC_HIP(hipMemsetAsync(w.cnt_e, 0, pad64(m) * 8, s));
+    BFC_HIP(hipGetLastError());
+    BFC_TRY(local_run(g, side, mark, nullptr, nullptr, (uint64_t *)w.cnt_e, w.local, w.local_bytes,
+                      s));
+    k_gather_edge<<<grid_for(k), 256, 0, s>>>(k, w.draw, w.cnt_e, (unsigned long long *)d_counts,
+                                              (unsigned long long *)d_eids);
+    BFC_HIP(hipGetLastError());
+    return finish_estimate(k, m, (unsigned long long *)d_counts, d_probs != nullptr, w, d_est, s);
+}
+
+}  // extern "C"
