@@ -192,6 +192,53 @@ int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t se
               uint64_t *d_eids, uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
               hipStream_t stream);
 
+/* ---------------------------------------------------------------------- */
+/* Learned importance sampling (an addition to the paper's VSamp): a small  */
+/* MLP predicts log1p(B_v) from per-vertex features; its predictions give   */
+/* bfc_vsamp's probabilities.  It never changes a count.                    */
+/*   parameters: bfc_mlp_param_count() floats, layout W1[8][64], b1[64],     */
+/*   W2[64][64], b2[64], w3[64], b3 (FP32 master copy; device, caller-owned); */
+/*   BF16 copy: the same count of uint16 at the same offsets (W1, W2, w3 are */
+/*   read from it).  Layers: h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2),     */
+/*   y = h2 w3 + b3, on the matrix cores in BF16 with FP32 accumulation; h1  */
+/*   is rounded to BF16 before layer 2.                                      */
+/* ---------------------------------------------------------------------- */
+int bfc_mlp_param_count(void);
+/* 8 BF16 features per vertex, rows by global id (L ids, then n_left + R id):
+ * side, log1p d, log1p sum d_u, log1p sum d_u^2, log1p max d_u,
+ * log1p sum(d_u - 1), log1p C(d,2), log1p(sum d_u / d) over the neighbours u,
+ * each log term divided by 8.  d_feat: (n_left + n_right) * 8 uint16. */
+int bfc_features(const bfc_graph *g, uint16_t *d_feat, hipStream_t stream);
+/* BF16 copy of the FP32 parameters (round to nearest even). */
+int bfc_mlp_bf16(const float *d_params, uint16_t *d_wbf16, hipStream_t stream);
+/* y[r] for rows r < rows of d_x (rows * 8 BF16). */
+int bfc_mlp_forward(const uint16_t *d_x, uint32_t rows, const float *d_params,
+                    const uint16_t *d_wbf16, float *d_y, hipStream_t stream);
+/* Training targets log1p(count) / 8 (FP32) from n uint64 per-vertex counts. */
+int bfc_mlp_targets(const uint64_t *d_counts, uint64_t n, float *d_target, hipStream_t stream);
+/* Mini-batch of `rows` (>= 1) rows; row r is feature row d_idx[r] with target
+ * d_target[d_idx[r]] (d_idx NULL: row r itself).  Writes the gradient of
+ * sum_r (y_r - t_r)^2 / rows with respect to every parameter into d_grad
+ * (param_count floats, overwritten) and sum_r (y_r - t_r)^2 into *d_loss.
+ * dZ2 and dZ1 are rounded to BF16 before the matrix-core products that use
+ * them.  Per-wave partial sums go to the workspace (bfc_mlp_grad_ws_size
+ * bytes) and are reduced in a fixed order, so results are reproducible. */
+int bfc_mlp_grad_ws_size(uint32_t rows, size_t *bytes);
+int bfc_mlp_grad(const uint16_t *d_x, const float *d_target, const uint32_t *d_idx,
+                 uint32_t rows, const float *d_params, const uint16_t *d_wbf16, float *d_grad,
+                 float *d_loss, void *d_ws, size_t ws_bytes, hipStream_t stream);
+/* One Adam step (moments d_m1, d_m2; step >= 1 for the bias correction) on
+ * the FP32 parameters, then the BF16 copy is refreshed. */
+int bfc_adam_step(float *d_params, float *d_m1, float *d_m2, const float *d_grad,
+                  uint16_t *d_wbf16, float lr, float beta1, float beta2, float eps,
+                  uint32_t step, hipStream_t stream);
+/* Probabilities for bfc_vsamp from predictions y (n floats, predicting
+ * log1p(B_v)/8): p_v = max(expm1(8 y_v), floor_frac * mean_v expm1(8 y_v)^+),
+ * the mean reduced in a fixed order; *d_mean (may be NULL) gets the mean. */
+int bfc_probs_ws_size(size_t *bytes);
+int bfc_probs_from_predictions(const float *d_y, uint64_t n, double floor_frac, double *d_probs,
+                               double *d_mean, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,20 @@ SIGNATURES = {
     "bfc_esamp_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
     "bfc_esamp": ([C.POINTER(bfc_graph), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_mlp_param_count": ([], C.c_int),
+    "bfc_features": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p], C.c_int),
+    "bfc_mlp_bf16": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "bfc_mlp_forward": ([C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                        C.c_int),
+    "bfc_mlp_targets": ([C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p], C.c_int),
+    "bfc_mlp_grad_ws_size": ([C.c_uint32, C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_mlp_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_adam_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                       C.c_float, C.c_float, C.c_float, C.c_uint32, C.c_void_p], C.c_int),
+    "bfc_probs_ws_size": ([C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_probs_from_predictions": ([C.c_void_p, C.c_uint64, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
 }
 
 _lib = None

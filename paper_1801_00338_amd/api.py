@@ -173,7 +173,10 @@ class Graph:
         est = torch.zeros(1, dtype=torch.float64, device=self.device)
         pp = None
         if probs is not None:
-            pt = torch.as_tensor(np.ascontiguousarray(probs, dtype=np.float64)).to(self.device)
+            if isinstance(probs, torch.Tensor):
+                pt = probs.to(device=self.device, dtype=torch.float64).contiguous()
+            else:
+                pt = torch.as_tensor(np.ascontiguousarray(probs, dtype=np.float64)).to(self.device)
             if pt.numel() != n:
                 raise ValueError("probs has the wrong length")
             pp = C.c_void_p(pt.data_ptr())

@@ -36,7 +36,8 @@ import subprocess
 import numpy as np
 
 __all__ = ["er", "chung_lu", "capped_expected_degrees", "biclique",
-           "disjoint_union", "Workload", "WORKLOADS", "make_workload", "build_native"]
+           "disjoint_union", "Workload", "WORKLOADS", "make_workload", "build_native",
+           "mlp_init", "batch_order", "training_graphs"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen_native.c")
@@ -195,3 +196,47 @@ def scaled_chung_lu(scale: float, seed: int = 2):
     m = max(1, int(round(50_000_000 * scale)))
     cap = max(2.0, 100_000 * math.sqrt(scale))
     return nl, nr, chung_lu(nl, nr, m, 2.1, 2.3, cap, seed)
+
+
+# ---------------------------------------------------------------- learned sampling inputs
+MLP_PARAMS = 4801     # W1[8][64], b1[64], W2[64][64], b2[64], w3[64], b3
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Seeded initial parameters of the 8 -> 64 -> 64 -> 1 network (float32).
+
+    Weights uniform in +-sqrt(6 / fan_in) (He), w3 in +-sqrt(3 / 64), biases 0.
+    """
+    rng = np.random.default_rng(seed)
+    p = np.zeros(MLP_PARAMS, np.float32)
+    p[0:512] = rng.uniform(-1, 1, 512) * math.sqrt(6 / 8)
+    p[576:4672] = rng.uniform(-1, 1, 4096) * math.sqrt(6 / 64)
+    p[4736:4800] = rng.uniform(-1, 1, 64) * math.sqrt(3 / 64)
+    return p
+
+
+def batch_order(seed: int, n: int, epoch: int) -> np.ndarray:
+    """A seeded permutation of range(n) (uint32) for one epoch of mini-batches."""
+    rng = np.random.default_rng([seed, epoch])
+    return rng.permutation(n).astype(np.uint32)
+
+
+def training_graphs(count: int, m_lo: int, m_hi: int, seed: int, ratio: float = 4.0,
+                    mean_degree: float = 8.0, gamma_l: float = 2.1, gamma_r: float = 2.3):
+    """``count`` Chung-Lu graphs with m log-spaced in [m_lo, m_hi] and |R| = ratio |L|.
+
+    Mean degree 2m / (|L| + |R|) = ``mean_degree``; graph j uses seed
+    (seed << 32) | (j + 1); the expected-degree cap is min(14 sqrt(m), |L| / 4)
+    (14 sqrt(m) is 100k at 50M edges).  Returns a list of (nl, nr, l, r).
+    """
+    out = []
+    ms = np.geomspace(m_lo, m_hi, count) if count > 1 else np.array([m_lo])
+    for j, m in enumerate(ms):
+        m = int(round(m))
+        n = 2.0 * m / mean_degree
+        nl = max(2, int(round(n / (1 + ratio))))
+        nr = max(2, int(round(n - nl)))
+        cap = max(2.0, min(100_000.0, 14.0 * math.sqrt(m), nl / 4))
+        l, r = chung_lu(nl, nr, m, gamma_l, gamma_r, cap, (seed << 32) | (j + 1))
+        out.append((nl, nr, l, r))
+    return out
