@@ -193,6 +193,93 @@ int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t se
               hipStream_t stream);
 
 /* ---------------------------------------------------------------------- */
+/* Batched exact counts: many graphs counted in one persistent launch.      */
+/*                                                                          */
+/* A batch is one disjoint union of parts, each oriented so that its start  */
+/* side (ExactBFC's side choice, Sec. 4, applied per part) is the union's L; */
+/* bfc_batch_union builds the union's edge list, bfc_graph_build its CSRs,  */
+/* and bfc_exact_parts counts every part with one plan and one launch per   */
+/* kernel class, returning each part's total.  Nothing here changes a      */
+/* count: a part's total equals bfc_exact on that graph alone.              */
+/* ---------------------------------------------------------------------- */
+/* Launch shape of the count kernels; 0 in a field means its default.      */
+typedef struct bfc_tuning {
+    uint32_t narrow_max;          /* starts of degree <= this take the one-wave kernel (1..255; 255) */
+    uint32_t chunk;               /* narrow starts taken from the queue at once (1..64; 4) */
+    uint32_t narrow_waves_per_cu; /* narrow grid, waves per compute unit (1..8; 8) */
+    uint32_t wide_groups_per_cu;  /* wide grid, workgroups per compute unit (1..2; 2) */
+} bfc_tuning;
+
+/* bfc_exact with a given launch shape (NULL: defaults); same result. */
+int bfc_exact_tuned(const bfc_graph *g, int side, const bfc_tuning *tuning, uint64_t *d_total,
+                    void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Per-part totals of a disjoint union counted from L.  d_part_l (device,
+ * nparts + 1 uint32, ascending): part q owns the L ids [d_part_l[q],
+ * d_part_l[q + 1]) and the caller guarantees that its edges stay inside the
+ * part.  d_totals (device, nparts uint64) receives each part's butterflies,
+ * summed in a fixed order.  Asynchronous (plan, count, sums: kernels only),
+ * so it may be captured into a HIP graph and replayed. */
+int bfc_exact_parts_ws_size(const bfc_graph *g, size_t *bytes);
+int bfc_exact_parts(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_l,
+                    const bfc_tuning *tuning, uint64_t *d_totals, void *d_ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* Autotuner: times candidate launch shapes of bfc_exact_tuned (nparts == 0,
+ * automatic side; d_totals needs one uint64) or of bfc_exact_parts on this
+ * batch, with events on the stream, and returns the fastest in *best (and
+ * its time in *best_ms).  Synchronous; not for use under stream capture. */
+int bfc_autotune_ws_size(const bfc_graph *g, size_t *bytes);
+int bfc_autotune(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_l,
+                 uint64_t *d_totals, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                 bfc_tuning *best, float *best_ms);
+
+/* Union of ng graphs.  Graph q has h_nl[q] x h_nr[q] vertices and the edges
+ * [h_eoff[q], h_eoff[q + 1]) of the concatenated device lists d_l, d_r (ids
+ * local to the graph).  Each graph starts from R iff its sum of squared L
+ * degrees is below its sum of squared R degrees (ExactBFC's rule); such a
+ * graph is entered with its sides exchanged (h_swapped[q] = 1).  Writes the
+ * union ids d_ul, d_ur (device, h_eoff[ng] each) and the host offsets
+ * h_part_l / h_part_r (ng + 1): union L ids of graph q are [h_part_l[q],
+ * h_part_l[q + 1]).  Synchronous.  Errors: BFC_E_ID_RANGE (a local id out of
+ * range), BFC_E_TOO_LARGE (union sides beyond 2^32 - 1 vertices). */
+int bfc_batch_union_ws_size(uint32_t ng, const uint32_t *h_nl, const uint32_t *h_nr,
+                            const uint64_t *h_eoff, size_t *bytes);
+int bfc_batch_union(uint32_t ng, const uint32_t *h_nl, const uint32_t *h_nr,
+                    const uint64_t *h_eoff, const uint32_t *d_l, const uint32_t *d_r,
+                    uint32_t *d_ul, uint32_t *d_ur, uint32_t *h_part_l, uint32_t *h_part_r,
+                    uint8_t *h_swapped, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Replica batches: many ESpar / ClrSpar replicas of one graph counted in   */
+/* one launch.  Each replica keeps the edges its single call would keep     */
+/* (same parameters, same seed, same random stream), its kept graph becomes */
+/* one part of a disjoint union (isolated vertices dropped, ids renumbered  */
+/* densely, oriented by ExactBFC's side rule), and bfc_exact_parts counts   */
+/* all parts.  d_beta[i] and d_est[i] equal what bfc_espar / bfc_clrspar    */
+/* return for replica i, bit for bit.                                       */
+#define BFC_REPLICA_ESPAR 0
+#define BFC_REPLICA_CLRSPAR 1
+typedef struct bfc_replica {
+    uint32_t kind;      /* BFC_REPLICA_ESPAR or BFC_REPLICA_CLRSPAR */
+    uint32_t ncolors;   /* ClrSpar: N >= 1 colours */
+    double p;           /* ESpar: keep probability, 0 < p <= 1 */
+    uint64_t seed;
+} bfc_replica;
+/* Phase 1 (synchronous): kept edges of each replica into h_kept (host, nrep). */
+int bfc_spar_batch_filter_ws_size(const bfc_graph *g, size_t *bytes);
+int bfc_spar_batch_filter(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
+                          uint64_t *h_kept, void *d_ws, size_t ws_bytes, hipStream_t stream);
+/* Phase 2 (synchronous): the batch itself; h_kept must be phase 1's output
+ * for the same graph and replicas (else BFC_E_ARG).  d_beta (nrep uint64) and
+ * d_est (nrep double) are device arrays.  BFC_E_TOO_LARGE when the union
+ * would exceed 32-bit ids. */
+int bfc_spar_batch_ws_size(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
+                           const uint64_t *h_kept, size_t *bytes);
+int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
+                   const uint64_t *h_kept, const bfc_tuning *tuning, uint64_t *d_beta,
+                   double *d_est, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
 /* Learned importance sampling (an addition to the paper's VSamp): a small  */
 /* MLP predicts log1p(B_v) from per-vertex features; its predictions give   */
 /* bfc_vsamp's probabilities.  It never changes a count.                    */

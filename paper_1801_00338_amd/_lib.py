@@ -37,6 +37,22 @@ class bfc_graph(C.Structure):
     ]
 
 
+class bfc_tuning(C.Structure):
+    _fields_ = [("narrow_max", C.c_uint32), ("chunk", C.c_uint32),
+                ("narrow_waves_per_cu", C.c_uint32), ("wide_groups_per_cu", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+BFC_REPLICA_ESPAR, BFC_REPLICA_CLRSPAR = 0, 1
+
+
+class bfc_replica(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("ncolors", C.c_uint32), ("p", C.c_double),
+                ("seed", C.c_uint64)]
+
+
 class BfcError(RuntimeError):
     def __init__(self, code, what=""):
         name = ERROR_NAMES.get(code, str(code))
@@ -83,6 +99,27 @@ SIGNATURES = {
     "bfc_esamp_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
     "bfc_esamp": ([C.POINTER(bfc_graph), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_exact_tuned": ([C.POINTER(bfc_graph), C.c_int, C.POINTER(bfc_tuning), C.c_void_p,
+                         C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_exact_parts_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_exact_parts": ([C.POINTER(bfc_graph), C.c_uint32, C.c_void_p, C.POINTER(bfc_tuning),
+                         C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_autotune_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_autotune": ([C.POINTER(bfc_graph), C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                      C.c_size_t, C.c_void_p, C.POINTER(bfc_tuning), C.POINTER(C.c_float)],
+                     C.c_int),
+    "bfc_batch_union_ws_size": ([C.c_uint32, u32p, u32p, u64p, C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_batch_union": ([C.c_uint32, u32p, u32p, u64p, C.c_void_p, C.c_void_p, C.c_void_p,
+                         C.c_void_p, u32p, u32p, C.POINTER(C.c_uint8), C.c_void_p, C.c_size_t,
+                         C.c_void_p], C.c_int),
+    "bfc_spar_batch_filter_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_spar_batch_filter": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica), u64p,
+                               C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_spar_batch_ws_size": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica), u64p,
+                                C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_spar_batch": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica), u64p,
+                        C.POINTER(bfc_tuning), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                        C.c_void_p], C.c_int),
     "bfc_mlp_param_count": ([], C.c_int),
     "bfc_features": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p], C.c_int),
     "bfc_mlp_bf16": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),

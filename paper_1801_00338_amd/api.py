@@ -200,12 +200,156 @@ class Graph:
         return self._samp(L.bfc_esamp_ws_size, L.bfc_esamp, self.n_edges, k, seed, probs,
                           torch.int64)
 
+    # -------------------------------------------------------------- batching
+    def exact_tuned(self, tuning=None, side=BFC_SIDE_AUTO):
+        """bfc_exact with a launch shape (a bfc_tuning, a dict of its fields, or None)."""
+        t = _tuning(tuning)
+        out = torch.zeros(1, dtype=torch.int64, device=self.device)
+        ws = self.workspace(self.exact_ws_size(side))
+        check(lib().bfc_exact_tuned(C.byref(self.g), side, C.byref(t) if t else None,
+                                    C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                    ws.numel(), _stream()), "exact tuned")
+        torch.cuda.synchronize(self.device)
+        return int(out.cpu().numpy().view(np.uint64)[0])
+
+    def autotune(self):
+        """Fastest launch shape for this graph: (bfc_tuning, milliseconds)."""
+        return _autotune(self, 0, None)
+
+    def spar_batch(self, replicas, tuning=None):
+        """Replicas [(kind, param, seed)] with kind "espar" (param p) or "clrspar" (param N),
+        counted in one batch: (counts uint64[n], estimates float64[n], kept edges uint64[n])."""
+        L = lib()
+        n = len(replicas)
+        reps = (_lib.bfc_replica * n)()
+        for i, (kind, param, seed) in enumerate(replicas):
+            if kind == "espar":
+                reps[i] = _lib.bfc_replica(_lib.BFC_REPLICA_ESPAR, 0, float(param), seed)
+            elif kind == "clrspar":
+                reps[i] = _lib.bfc_replica(_lib.BFC_REPLICA_CLRSPAR, int(param), 0.0, seed)
+            else:
+                raise ValueError(kind)
+        sz = C.c_size_t()
+        check(L.bfc_spar_batch_filter_ws_size(C.byref(self.g), C.byref(sz)), "filter ws size")
+        ws = _bytes(sz.value, self.device)
+        kept = (C.c_uint64 * n)()
+        check(L.bfc_spar_batch_filter(C.byref(self.g), n, reps, kept, C.c_void_p(ws.data_ptr()),
+                                      ws.numel(), _stream()), "batch filter")
+        del ws
+        check(L.bfc_spar_batch_ws_size(C.byref(self.g), n, reps, kept, C.byref(sz)),
+              "batch ws size")
+        ws = _bytes(sz.value, self.device)
+        beta = torch.zeros(n, dtype=torch.int64, device=self.device)
+        est = torch.zeros(n, dtype=torch.float64, device=self.device)
+        t = _tuning(tuning)
+        check(L.bfc_spar_batch(C.byref(self.g), n, reps, kept, C.byref(t) if t else None,
+                               C.c_void_p(beta.data_ptr()), C.c_void_p(est.data_ptr()),
+                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "spar batch")
+        torch.cuda.synchronize(self.device)
+        return (beta.cpu().numpy().view(np.uint64).copy(), est.cpu().numpy().copy(),
+                np.array(kept[:], dtype=np.uint64))
+
     def per_vertex(self):
         cl, cr, _ = self.local(vertices=True, edges=False)
         return cl, cr
 
     def per_edge(self):
         return self.local(vertices=False, edges=True)[2]
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, _lib.bfc_tuning):
+        return t
+    return _lib.bfc_tuning(**t)
+
+
+def _autotune(graph, nparts, part_l):
+    L = lib()
+    sz = C.c_size_t()
+    check(L.bfc_autotune_ws_size(C.byref(graph.g), C.byref(sz)), "autotune ws size")
+    ws = _bytes(sz.value, graph.device)
+    out = torch.zeros(max(nparts, 1), dtype=torch.int64, device=graph.device)
+    best = _lib.bfc_tuning()
+    ms = C.c_float()
+    check(L.bfc_autotune(C.byref(graph.g), nparts,
+                         C.c_void_p(part_l.data_ptr()) if part_l is not None else None,
+                         C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                         _stream(), C.byref(best), C.byref(ms)), "autotune")
+    return best, ms.value
+
+
+class Batch:
+    """Many bipartite graphs as one disjoint union, counted in one launch.
+
+    ``graphs`` holds (n_left, n_right, l, r) tuples with ids local to each
+    graph.  Each graph enters the union with its start side (ExactBFC's rule)
+    as the union's L; ``swapped[q]`` tells whether its sides were exchanged.
+    """
+
+    def __init__(self, graphs, device="cuda"):
+        L = lib()
+        self.device = torch.device(device)
+        ng = len(graphs)
+        nl = np.array([g[0] for g in graphs], dtype=np.uint32)
+        nr = np.array([g[1] for g in graphs], dtype=np.uint32)
+        eoff = np.zeros(ng + 1, dtype=np.uint64)
+        eoff[1:] = np.cumsum([len(g[2]) for g in graphs])
+        l = np.concatenate([np.asarray(g[2], np.uint32) for g in graphs]) if ng else np.zeros(0)
+        r = np.concatenate([np.asarray(g[3], np.uint32) for g in graphs]) if ng else np.zeros(0)
+        dl = to_device_u32(l, self.device)
+        dr = to_device_u32(r, self.device)
+        m = int(eoff[-1])
+        ul = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        ur = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        part_l = np.zeros(ng + 1, dtype=np.uint32)
+        part_r = np.zeros(ng + 1, dtype=np.uint32)
+        swapped = np.zeros(max(ng, 1), dtype=np.uint8)
+        p32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_uint32))
+        sz = C.c_size_t()
+        check(L.bfc_batch_union_ws_size(ng, p32(nl), p32(nr),
+                                        eoff.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                        C.byref(sz)), "union ws size")
+        ws = _bytes(sz.value, self.device)
+        check(L.bfc_batch_union(ng, p32(nl), p32(nr), eoff.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                C.c_void_p(dl.data_ptr()), C.c_void_p(dr.data_ptr()),
+                                C.c_void_p(ul.data_ptr()), C.c_void_p(ur.data_ptr()),
+                                p32(part_l), p32(part_r),
+                                swapped.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "batch union")
+        del ws, dl, dr
+        self.n_graphs = ng
+        self.part_l_host, self.part_r_host = part_l, part_r
+        self.swapped = swapped[:ng].astype(bool)
+        self.graph = Graph(int(part_l[-1]), int(part_r[-1]), ul[:m], ur[:m], device=self.device)
+        del ul, ur
+        self.part_l = to_device_u32(part_l, self.device)
+        check(L.bfc_exact_parts_ws_size(C.byref(self.graph.g), C.byref(sz)), "parts ws size")
+        self.ws = _bytes(sz.value, self.device)
+
+    @property
+    def wedges(self):
+        return self.graph.wedges(BFC_SIDE_L)
+
+    def totals_async(self, out, tuning=None, stream=None):
+        """Queue the per-graph counts into ``out`` (int64 device tensor, n_graphs)."""
+        t = _tuning(tuning)
+        check(lib().bfc_exact_parts(C.byref(self.graph.g), self.n_graphs,
+                                    C.c_void_p(self.part_l.data_ptr()),
+                                    C.byref(t) if t else None, C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                    _stream(stream)), "exact parts")
+        return out
+
+    def totals(self, tuning=None):
+        out = torch.zeros(max(self.n_graphs, 1), dtype=torch.int64, device=self.device)
+        self.totals_async(out, tuning)
+        torch.cuda.synchronize(self.device)
+        return out.cpu().numpy().view(np.uint64)[:self.n_graphs].copy()
+
+    def autotune(self):
+        return _autotune(self.graph, self.n_graphs, self.part_l)
 
 
 def exact(n_left, n_right, l, r, side=BFC_SIDE_AUTO):

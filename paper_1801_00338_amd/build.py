@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["graph_build.hip", "count.hip", "estimators.hip", "learned.hip"]
+SOURCES = ["graph_build.hip", "count.hip", "estimators.hip", "batch.hip", "learned.hip"]
 LIB = os.path.join(HERE, "libbfc.so")
 
 FLAGS = [

@@ -38,14 +38,14 @@ namespace bfc {
 constexpr uint32_t INF = 0xFFFFFFFFu;
 constexpr int NBUCKET = 66;
 constexpr int G_SHIFT = 14;             // window = 2^14 ranks (segment granularity)
-constexpr uint32_t NARROW_MAX = 255;    // byte counters: C_u[w] <= d_u <= 255
+constexpr uint32_t NARROW_MAX = 255;    // byte counters: C_u[w] <= d_u <= 255 (largest threshold)
 
 // narrow kernels: one wave per workgroup
 constexpr int WT = 64;
 constexpr int WTBL_BYTES = 1 << G_SHIFT;
 constexpr uint32_t WTBL_WORDS = WTBL_BYTES / 4;
 constexpr int WSLOTS = 4;               // midpoints per lane (4 * 64 > NARROW_MAX)
-constexpr int WCHUNK = 4;               // starts taken from the queue at once
+constexpr int WCHUNK = 4;               // default starts taken from the queue at once
 
 // wide kernels: 512-lane workgroups
 constexpr int NT = 512;
@@ -127,7 +127,8 @@ struct QueueState {
 __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32_t *adjA,
                                               const uint32_t *xA, const uint32_t *offB,
                                               uint32_t nA, int all_ends, const uint8_t *mark,
-                                              uint8_t *bucket, QueueState *q) {
+                                              uint32_t narrow_max, uint8_t *bucket,
+                                              QueueState *q) {
     __shared__ uint32_t hist[2][NBUCKET];
     for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
     __syncthreads();
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
         t = wave_sum64(t);
         if (lane == 0) {
             uint32_t b = t ? 64 - __clzll(t) : 0;
-            uint32_t cls = (re - rb) > NARROW_MAX;
+            uint32_t cls = (re - rb) > narrow_max;
             bucket[u] = (uint8_t)(b | cls << 7);
             if (b) atomicAdd(&hist[cls][b], 1u);
         }
@@ -231,7 +232,9 @@ struct CountArgs {
     const uint32_t *items, *items_wide;
     QueueState *q;
     uint32_t nA;
+    uint32_t chunk;                     // narrow starts per queue access
     unsigned long long *total;
+    unsigned long long *per_start;      // butterflies found from each start (rank), or null
 };
 
 // Local counts.  For a start u the walk takes every endpoint w != u (no
@@ -518,10 +521,10 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
     return sum;
 }
 
-// Hand out WCHUNK starts per queue access.
-__device__ inline uint32_t wave_take(QueueState *q, int cls) {
+// Hand out `chunk` starts per queue access.
+__device__ inline uint32_t wave_take(QueueState *q, int cls, uint32_t chunk) {
     uint32_t b = 0;
-    if (threadIdx.x == 0) b = atomicAdd(&q->head[cls], (uint32_t)WCHUNK);
+    if (threadIdx.x == 0) b = atomicAdd(&q->head[cls], chunk);
     return __shfl(b, 0, WT);
 }
 
@@ -532,12 +535,17 @@ __global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
     __syncthreads();
     const uint32_t n = a.q->n_items[0];
     unsigned long long acc = 0;
-    for (uint32_t b = wave_take(a.q, 0); b < n; b = wave_take(a.q, 0)) {
-        const uint32_t e = b + WCHUNK < n ? b + WCHUNK : n;
+    for (uint32_t b = wave_take(a.q, 0, a.chunk); b < n; b = wave_take(a.q, 0, a.chunk)) {
+        const uint32_t e = b + a.chunk < n ? b + a.chunk : n;
         for (uint32_t it = b; it < e; it++) {
             const uint32_t u = a.items[it];
             const uint32_t rb = a.offA[u];
-            acc += wave_walk<false>(a, sh, rb, a.offA[u + 1] - rb, false);
+            const unsigned long long s = wave_walk<false>(a, sh, rb, a.offA[u + 1] - rb, false);
+            if (a.per_start) {
+                const unsigned long long t = wave_sum64(s);
+                if (threadIdx.x == 0) a.per_start[u] = t;
+            }
+            acc += s;
         }
     }
     acc = wave_sum64(acc);
@@ -550,8 +558,8 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
     sh.tbl[WTBL_WORDS + threadIdx.x] = 0;
     __syncthreads();
     const uint32_t n = a.c.q->n_items[0];
-    for (uint32_t b = wave_take(a.c.q, 0); b < n; b = wave_take(a.c.q, 0)) {
-        const uint32_t e = b + WCHUNK < n ? b + WCHUNK : n;
+    for (uint32_t b = wave_take(a.c.q, 0, a.c.chunk); b < n; b = wave_take(a.c.q, 0, a.c.chunk)) {
+        const uint32_t e = b + a.c.chunk < n ? b + a.c.chunk : n;
         for (uint32_t it = b; it < e; it++) {
             const uint32_t u = a.c.items[it];
             const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
@@ -764,7 +772,12 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
     for (uint32_t it = block_take(sh, a.q); it < n; it = block_take(sh, a.q)) {
         const uint32_t u = a.items_wide[it];
         const uint32_t rb = a.offA[u];
-        acc += walk_wide<false>(a, sh, rb, a.offA[u + 1] - rb, ws, false);
+        const unsigned long long s = walk_wide<false>(a, sh, rb, a.offA[u + 1] - rb, ws, false);
+        if (a.per_start) {
+            const unsigned long long t = block_sum64<NT>(s, sh.red64);
+            if (threadIdx.x == 0) a.per_start[u] = t;
+        }
+        acc += s;
     }
     acc = block_sum64<NT>(acc, sh.red64);
     finish_launch(a.q, 1, acc, a.total);
@@ -792,6 +805,22 @@ __global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a, WideScratch ws) 
         if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = s;
     }
     finish_launch(a.c.q, 1, 0, nullptr);
+}
+
+// Per-part totals of a disjoint union counted from L: part q owns the L ids
+// [part_l[q], part_l[q + 1]); its total is the sum of its starts' counts,
+// added in a fixed order (strided per thread, then the block reduction).
+__global__ __launch_bounds__(256) void k_part_sums(const unsigned long long *per_start,
+                                                   const uint32_t *rank_l, const uint32_t *part_l,
+                                                   uint32_t nparts, unsigned long long *totals) {
+    __shared__ unsigned long long red[256 / WAVE];
+    for (uint32_t q = blockIdx.x; q < nparts; q += gridDim.x) {
+        unsigned long long t = 0;
+        for (uint32_t id = part_l[q] + threadIdx.x; id < part_l[q + 1]; id += blockDim.x)
+            t += per_start[rank_l[id]];
+        t = block_sum64<256>(t, red);
+        if (threadIdx.x == 0) totals[q] = t;
+    }
 }
 
 // B_v of the midpoint side from the edge sums; outputs in caller ids.
@@ -840,7 +869,8 @@ static bool overflow_risk(uint64_t wedges, uint32_t max_deg) {
 }
 
 // Segments, per-start work buckets and the work queues for one plan.
-static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark, hipStream_t s) {
+static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark, hipStream_t s,
+                   uint32_t narrow_max = NARROW_MAX) {
     k_zero_u32<<<1, 256, 0, s>>>((uint32_t *)w.q, (uint64_t)(sizeof(QueueState) / 4));
     if (p.m) {
         k_seg_flags<<<grid_for(p.m), 256, 0, s>>>(p.adjB, p.m, w.seg1);
@@ -853,8 +883,8 @@ static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark,
     if (p.nA) {
         unsigned g = grid_for(p.nA, 4);
         if (g > 8192) g = 8192;
-        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.nA, all_ends, mark, w.bucket,
-                                 w.q);
+        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.nA, all_ends, mark, narrow_max,
+                                 w.bucket, w.q);
         BFC_HIP(hipGetLastError());
     }
     k_bucket_offsets<<<1, 64, 0, s>>>(w.q);
@@ -868,15 +898,36 @@ static void fill_args(const Plan &p, const ExactWs &w, CountArgs &a) {
     a.offA = p.offA; a.adjA = p.adjA; a.xA = p.xA; a.offB = p.offB; a.adjB = p.adjB;
     a.seg1 = w.seg1; a.seg_start = w.seg_start; a.seg_win = w.seg_win;
     a.items = w.items; a.items_wide = w.items_wide; a.q = w.q; a.nA = p.nA; a.total = nullptr;
+    a.chunk = WCHUNK; a.per_start = nullptr;
 }
 
-// Waves of the narrow grid per CU (LDS bound) and workgroups of the wide grid.
-static int grids(unsigned &narrow, unsigned &wide) {
+// Tuning with defaults filled in and ranges checked.
+static int resolve_tuning(const bfc_tuning *t, bfc_tuning &r) {
+    r.narrow_max = NARROW_MAX;
+    r.chunk = WCHUNK;
+    r.narrow_waves_per_cu = 8;
+    r.wide_groups_per_cu = 2;
+    if (!t) return BFC_OK;
+    if (t->narrow_max) r.narrow_max = t->narrow_max;
+    if (t->chunk) r.chunk = t->chunk;
+    if (t->narrow_waves_per_cu) r.narrow_waves_per_cu = t->narrow_waves_per_cu;
+    if (t->wide_groups_per_cu) r.wide_groups_per_cu = t->wide_groups_per_cu;
+    if (r.narrow_max > NARROW_MAX || r.chunk > 64 || r.narrow_waves_per_cu > 8 ||
+        r.wide_groups_per_cu > 2)
+        return BFC_E_ARG;
+    return BFC_OK;
+}
+
+// Waves of the narrow grid per CU (LDS bound: eight 16 KiB tables) and
+// workgroups of the wide grid (two 64 KiB tables).
+static int grids(unsigned &narrow, unsigned &wide, const bfc_tuning *t = nullptr) {
+    bfc_tuning r;
+    BFC_TRY(resolve_tuning(t, r));
     int dev = 0;
     BFC_HIP(hipGetDevice(&dev));
     const unsigned cu = (unsigned)device_cu_count(dev);
-    narrow = cu * 8;
-    wide = cu * 2;
+    narrow = cu * r.narrow_waves_per_cu;
+    wide = cu * r.wide_groups_per_cu;
     return BFC_OK;
 }
 
@@ -971,6 +1022,30 @@ int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt
     return BFC_OK;
 }
 
+// The two persistent launches of one count on a planned workspace.
+static int launch_count(const Plan &p, const ExactWs &w, const bfc_tuning *t,
+                        unsigned long long *total, unsigned long long *per_start, hipStream_t s) {
+    if (p.nA == 0 || p.m == 0) {
+        k_zero_u64<<<1, 64, 0, s>>>(total, 1);
+        BFC_HIP(hipGetLastError());
+        return BFC_OK;
+    }
+    bfc_tuning r;
+    BFC_TRY(resolve_tuning(t, r));
+    CountArgs a;
+    fill_args(p, w, a);
+    a.chunk = r.chunk;
+    a.per_start = per_start;
+    unsigned gn, gw;
+    BFC_TRY(grids(gn, gw, &r));
+    k_exact_narrow<<<gn, WT, 0, s>>>(a);
+    a.total = total;
+    WideScratch ws = {w.wpos, w.wseg, nullptr, nullptr, nullptr};
+    k_exact_wide<<<gw, NT, 0, s>>>(a, ws);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
 }  // namespace bfc
 
 using namespace bfc;
@@ -1015,22 +1090,7 @@ int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws,
     Plan p;
     ExactWs w;
     BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
-    unsigned long long *tot = (unsigned long long *)d_total;
-    if (p.nA == 0 || p.m == 0) {
-        k_zero_u64<<<1, 64, 0, s>>>(tot, 1);
-        BFC_HIP(hipGetLastError());
-        return BFC_OK;
-    }
-    CountArgs a;
-    fill_args(p, w, a);
-    unsigned gn, gw;
-    BFC_TRY(grids(gn, gw));
-    k_exact_narrow<<<gn, WT, 0, s>>>(a);
-    a.total = tot;
-    WideScratch ws = {w.wpos, w.wseg, nullptr, nullptr, nullptr};
-    k_exact_wide<<<gw, NT, 0, s>>>(a, ws);
-    BFC_HIP(hipGetLastError());
-    return BFC_OK;
+    return launch_count(p, w, nullptr, (unsigned long long *)d_total, nullptr, s);
 }
 
 int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws, size_t ws_bytes,
@@ -1038,6 +1098,138 @@ int bfc_exact(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws, size_
     if (!d_total) return BFC_E_NULL;
     BFC_TRY(bfc_exact_plan(g, side, d_ws, ws_bytes, s));
     return bfc_exact_count(g, side, d_total, d_ws, ws_bytes, s);
+}
+
+int bfc_exact_tuned(const bfc_graph *g, int side, const bfc_tuning *t, uint64_t *d_total,
+                    void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!d_total) return BFC_E_NULL;
+    if ((uintptr_t)d_total & 7) return BFC_E_ALIGN;
+    bfc_tuning r;
+    BFC_TRY(resolve_tuning(t, r));
+    Plan p;
+    ExactWs w;
+    BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
+    BFC_TRY(prepare(p, w, 0, nullptr, s, r.narrow_max));
+    return launch_count(p, w, &r, (unsigned long long *)d_total, nullptr, s);
+}
+
+int bfc_exact_parts_ws_size(const bfc_graph *g, size_t *bytes) {
+    if (!bytes) return BFC_E_NULL;
+    Plan p;
+    BFC_TRY(make_plan(g, BFC_SIDE_L, &p));
+    Carver c(nullptr, 0);
+    carve_exact(c, p);
+    c.take<unsigned long long>(pad64(p.nA));
+    c.take<unsigned long long>(1);
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_exact_parts(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_l,
+                    const bfc_tuning *t, uint64_t *d_totals, void *d_ws, size_t ws_bytes,
+                    hipStream_t s) {
+    if (!g || !d_part_l || !d_totals || !d_ws) return BFC_E_NULL;
+    if (nparts == 0) return BFC_E_ARG;
+    if ((uintptr_t)d_totals & 7) return BFC_E_ALIGN;
+    bfc_tuning r;
+    BFC_TRY(resolve_tuning(t, r));
+    Plan p;
+    ExactWs w;
+    BFC_TRY(exact_setup(g, BFC_SIDE_L, d_ws, ws_bytes, p, w));
+    Carver c(d_ws, ws_bytes);
+    carve_exact(c, p);
+    unsigned long long *per_start = c.take<unsigned long long>(pad64(p.nA));
+    unsigned long long *total = c.take<unsigned long long>(1);
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    k_zero_u64<<<grid_for(p.nA), 256, 0, s>>>(per_start, p.nA);
+    BFC_HIP(hipGetLastError());
+    BFC_TRY(prepare(p, w, 0, nullptr, s, r.narrow_max));
+    BFC_TRY(launch_count(p, w, &r, total, per_start, s));
+    unsigned gp = nparts < 65535u ? nparts : 65535u;
+    k_part_sums<<<gp, 256, 0, s>>>(per_start, g->rank_l, d_part_l, nparts,
+                                   (unsigned long long *)d_totals);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+int bfc_autotune_ws_size(const bfc_graph *g, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    size_t a = 0, b = 0;
+    BFC_TRY(bfc_exact_parts_ws_size(g, &a));
+    BFC_TRY(bfc_exact_ws_size(g, BFC_SIDE_AUTO, &b));
+    b += 256;
+    *bytes = a > b ? a : b;
+    return BFC_OK;
+}
+
+// Times candidate tunings on this graph (nparts == 0: bfc_exact_tuned with
+// the automatic side) or this batch (bfc_exact_parts) and returns the
+// fastest.  Two stages: the narrow/wide threshold with the queue chunk, then
+// the grid shapes for the best of those.  Each candidate runs once untimed
+// and three times timed with events on the stream; the minimum counts.
+int bfc_autotune(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_l,
+                 uint64_t *d_totals, void *d_ws, size_t ws_bytes, hipStream_t s,
+                 bfc_tuning *best, float *best_ms) {
+    if (!g || !d_ws || !best || !d_totals) return BFC_E_NULL;
+    if (nparts && !d_part_l) return BFC_E_NULL;
+    size_t need = 0;
+    BFC_TRY(bfc_autotune_ws_size(g, &need));
+    if (ws_bytes < need) return BFC_E_WS_SMALL;
+    hipEvent_t e0, e1;
+    BFC_HIP(hipEventCreate(&e0));
+    BFC_HIP(hipEventCreate(&e1));
+    auto run = [&](const bfc_tuning &t) -> int {
+        if (nparts) return bfc_exact_parts(g, nparts, d_part_l, &t, d_totals, d_ws, ws_bytes, s);
+        return bfc_exact_tuned(g, BFC_SIDE_AUTO, &t, d_totals, d_ws, ws_bytes, s);
+    };
+    auto time_one = [&](const bfc_tuning &t, float &ms) -> int {
+        BFC_TRY(run(t));
+        float bestm = 3.4e38f;
+        for (int i = 0; i < 3; i++) {
+            BFC_HIP(hipEventRecord(e0, s));
+            BFC_TRY(run(t));
+            BFC_HIP(hipEventRecord(e1, s));
+            BFC_HIP(hipEventSynchronize(e1));
+            float x = 0.f;
+            BFC_HIP(hipEventElapsedTime(&x, e0, e1));
+            if (x < bestm) bestm = x;
+        }
+        ms = bestm;
+        return BFC_OK;
+    };
+    bfc_tuning cur = {NARROW_MAX, (uint32_t)WCHUNK, 8, 2};
+    float cur_ms = 3.4e38f;
+    int rc = BFC_OK;
+    const uint32_t thresholds[] = {255, 127, 63, 31};
+    const uint32_t chunks[] = {1, 4, 16};
+    for (uint32_t nm : thresholds)
+        for (uint32_t ch : chunks) {
+            bfc_tuning t = {nm, ch, 8, 2};
+            float ms;
+            if ((rc = time_one(t, ms)) != BFC_OK) goto out;
+            if (ms < cur_ms) { cur_ms = ms; cur = t; }
+        }
+    {
+        const uint32_t nw[] = {8, 6, 4};
+        const uint32_t wg[] = {2, 1};
+        const bfc_tuning base = cur;
+        for (uint32_t a : nw)
+            for (uint32_t b : wg) {
+                if (a == base.narrow_waves_per_cu && b == base.wide_groups_per_cu) continue;
+                bfc_tuning t = base;
+                t.narrow_waves_per_cu = a;
+                t.wide_groups_per_cu = b;
+                float ms;
+                if ((rc = time_one(t, ms)) != BFC_OK) goto out;
+                if (ms < cur_ms) { cur_ms = ms; cur = t; }
+            }
+    }
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+out:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int bfc_local_ws_size(const bfc_graph *g, size_t *bytes) {

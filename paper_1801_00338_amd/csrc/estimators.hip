@@ -19,6 +19,8 @@
 // below the total Q.
 #include "common.h"
 
+#include <vector>
+
 namespace bfc {
 
 constexpr uint32_t TAG_ESPAR = 0x45535052u;
@@ -101,15 +103,16 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs f, uint32_t *flag) {
     }
 }
 
-// Kept edges, compacted by the inclusive scan of the flags (same row walk).
+// Kept edges, compacted by the inclusive scan of the flags (same row walk);
+// at most `cap` of them are written.
 __global__ __launch_bounds__(256) void k_compact(FilterArgs f, const uint32_t *scan1,
-                                                 uint32_t *kl, uint32_t *kr) {
+                                                 uint32_t *kl, uint32_t *kr, uint32_t cap) {
     const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
     for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < f.nl; u += gridDim.x * wpb) {
         const uint32_t l = f.id_l[u];
         for (uint32_t k = f.off_l[u] + lane; k < f.off_l[u + 1]; k += WAVE) {
             const uint32_t prev = k ? scan1[k - 1] : 0;
-            if (scan1[k] != prev) {
+            if (scan1[k] != prev && prev < cap) {
                 kl[prev] = l;
                 kr[prev] = f.id_r[f.adj_l[k]];
             }
@@ -406,7 +409,7 @@ static int sparsify_count(const bfc_graph *g, FilterArgs f, SparWs &w, uint64_t 
         k_filter<<<gr, 256, 0, s>>>(f, w.flag);
         BFC_HIP(hipGetLastError());
         BFC_TRY(scan_u32_inclusive(w.flag, w.flag, m, w.scan_tmp, s));
-        k_compact<<<gr, 256, 0, s>>>(f, w.flag, w.kl, w.kr);
+        k_compact<<<gr, 256, 0, s>>>(f, w.flag, w.kl, w.kr, 0xFFFFFFFFu);
         BFC_HIP(hipGetLastError());
         uint32_t last = 0;
         BFC_HIP(hipMemcpyAsync(&last, w.flag + (m - 1), 4, hipMemcpyDeviceToHost, s));
@@ -483,6 +486,321 @@ int bfc_clrspar(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint64_t *d
     const double N = (double)ncolors;
     k_est_scale<<<1, 64, 0, s>>>((unsigned long long *)d_beta, 0.0, N * N * N, d_est);
     BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ host: replica batches
+// Many ESpar / ClrSpar replicas of one graph counted in one launch: each
+// replica's kept edges are compacted into a shared pool with its vertices
+// renumbered densely (isolated vertices dropped: they carry no butterfly),
+// the replicas become the parts of one disjoint union (each oriented by
+// ExactBFC's side rule) and bfc_exact_parts counts them together.  Every
+// replica's count and estimate equal those of bfc_espar / bfc_clrspar with
+// the same parameters and seed.
+namespace bfc {
+
+__global__ void k_mark_ends(const uint32_t *kl, const uint32_t *kr, uint64_t mk, uint32_t *ml,
+                            uint32_t *mr) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < mk;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        ml[kl[e]] = 1u;
+        mr[kr[e]] = 1u;
+    }
+}
+
+// New id = (inclusive scan of the marks at the old id) - 1.
+__global__ void k_renumber(uint32_t *kl, uint32_t *kr, uint64_t mk, const uint32_t *sl,
+                           const uint32_t *sr) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < mk;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        kl[e] = sl[kl[e]] - 1u;
+        kr[e] = sr[kr[e]] - 1u;
+    }
+}
+
+__global__ void k_store_last(const uint32_t *scan, uint64_t n, uint32_t *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = n ? scan[n - 1] : 0u;
+}
+
+__global__ void k_zero32(uint32_t *p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_est_batch(const unsigned long long *beta, const double *div, const double *mul,
+                            uint32_t n, double *est) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double b = (double)beta[i];
+        est[i] = div[i] != 0.0 ? b / div[i] : b * mul[i];
+    }
+}
+
+static int check_replicas(uint32_t nrep, const bfc_replica *reps) {
+    if (!reps) return BFC_E_NULL;
+    if (nrep == 0) return BFC_E_ARG;
+    for (uint32_t i = 0; i < nrep; i++) {
+        const bfc_replica &r = reps[i];
+        if (r.kind == BFC_REPLICA_ESPAR) {
+            if (!(r.p > 0.0) || !(r.p <= 1.0)) return BFC_E_ARG;
+        } else if (r.kind == BFC_REPLICA_CLRSPAR) {
+            if (r.ncolors == 0) return BFC_E_ARG;
+        } else {
+            return BFC_E_ARG;
+        }
+    }
+    return BFC_OK;
+}
+
+struct FilterWs {
+    uint32_t *flag, *scan_tmp, *col_l, *col_r;
+};
+
+static void carve_filter(Carver &c, const bfc_graph *g, FilterWs &w) {
+    w.flag = c.take<uint32_t>(pad64(g->n_edges));
+    w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(g->n_edges));
+    w.col_l = c.take<uint32_t>(pad64(g->n_left));
+    w.col_r = c.take<uint32_t>(pad64(g->n_right));
+}
+
+// Keep flags of replica `rep` in w.flag, then their inclusive scan.
+static int filter_replica(const bfc_graph *g, const bfc_replica &rep, FilterWs &w,
+                          FilterArgs &f, hipStream_t s) {
+    f = FilterArgs{};
+    f.off_l = g->off_l; f.adj_l = g->adj_l; f.id_l = g->id_l; f.id_r = g->id_r;
+    f.nl = g->n_left;
+    f.seed = rep.seed;
+    if (rep.kind == BFC_REPLICA_ESPAR) {
+        f.kind = 0;
+        f.keep_all = rep.p >= 1.0;
+        f.thresh = f.keep_all ? 0 : (uint64_t)ldexp(rep.p, 64);
+    } else {
+        f.kind = 1;
+        f.keep_all = rep.ncolors == 1;
+        f.col_l = w.col_l;
+        f.col_r = w.col_r;
+        if (!f.keep_all) {
+            if (g->n_left)
+                k_colours<<<grid_for(g->n_left), 256, 0, s>>>(g->n_left, 0, rep.ncolors, rep.seed,
+                                                              w.col_l);
+            if (g->n_right)
+                k_colours<<<grid_for(g->n_right), 256, 0, s>>>(g->n_right, 1, rep.ncolors,
+                                                               rep.seed, w.col_r);
+        }
+    }
+    const uint64_t m = g->n_edges;
+    if (m) {
+        unsigned gr = grid_for(g->n_left, 4);
+        if (gr > 8192) gr = 8192;
+        k_filter<<<gr, 256, 0, s>>>(f, w.flag);
+        BFC_HIP(hipGetLastError());
+        BFC_TRY(scan_u32_inclusive(w.flag, w.flag, m, w.scan_tmp, s));
+    }
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+struct BatchWs {
+    FilterWs f;
+    uint32_t *ml, *mr, *scan_tmp_v, *kl, *kr, *kept_dev, *sizes_dev, *part_l;
+    double *div, *mul;
+    void *storage;
+    size_t storage_bytes;
+    void *work;
+    size_t work_bytes;
+};
+
+// Bounds of the union: part i has at most min(n, kept_i) vertices per side,
+// and either side may become the union's L.
+static int batch_bounds(const bfc_graph *g, uint32_t nrep, const uint64_t *h_kept, uint64_t &M,
+                        uint64_t &NV) {
+    M = NV = 0;
+    for (uint32_t i = 0; i < nrep; i++) {
+        const uint64_t k = h_kept[i];
+        const uint64_t a = k < g->n_left ? k : g->n_left, b = k < g->n_right ? k : g->n_right;
+        M += k;
+        NV += a > b ? a : b;
+    }
+    if (M > 0xFFFFFFFFull - ADJ_SLACK || NV > 0xFFFFFFFEull) return BFC_E_TOO_LARGE;
+    return BFC_OK;
+}
+
+static int carve_batch(Carver &c, const bfc_graph *g, uint32_t nrep, const uint64_t *h_kept,
+                       BatchWs &w) {
+    uint64_t M, NV;
+    BFC_TRY(batch_bounds(g, nrep, h_kept, M, NV));
+    carve_filter(c, g, w.f);
+    const uint64_t nv = (uint64_t)g->n_left > g->n_right ? g->n_left : g->n_right;
+    w.ml = c.take<uint32_t>(pad64(g->n_left));
+    w.mr = c.take<uint32_t>(pad64(g->n_right));
+    w.scan_tmp_v = c.take<uint32_t>(scan_tmp_elems(nv));
+    w.kl = c.take<uint32_t>(pad64(M));
+    w.kr = c.take<uint32_t>(pad64(M));
+    w.kept_dev = c.take<uint32_t>(nrep);
+    w.sizes_dev = c.take<uint32_t>(2 * (uint64_t)nrep);
+    w.part_l = c.take<uint32_t>(nrep + 1);
+    w.div = c.take<double>(nrep);
+    w.mul = c.take<double>(nrep);
+    size_t sb, bb, ub, pb;
+    BFC_TRY(bfc_graph_storage_size((uint32_t)NV, (uint32_t)NV, M, &sb));
+    BFC_TRY(bfc_graph_build_ws_size((uint32_t)NV, (uint32_t)NV, M, &bb));
+    // union workspace: offsets per part plus degree slots for both sides
+    {
+        Carver u(nullptr, 0);
+        u.take<uint64_t>(3 * ((uint64_t)nrep + 1));
+        u.take<uint32_t>(pad64(NV));
+        u.take<uint32_t>(pad64(NV));
+        u.take<uint32_t>(3 * ((uint64_t)nrep + 1));
+        u.take<uint8_t>(nrep + 1);
+        u.take<unsigned long long>(2 * (uint64_t)nrep);
+        ub = u.used + 16 * 256;     // the union carves these in more, separately rounded pieces
+    }
+    {
+        // bfc_exact_parts on a graph of these sizes, counted from L
+        Carver e(nullptr, 0);
+        e.take<char>(exact_ws_bound((uint32_t)NV, (uint32_t)NV, M));
+        e.take<unsigned long long>(pad64(NV));
+        e.take<unsigned long long>(1);
+        pb = e.used;
+    }
+    w.storage_bytes = sb;
+    w.storage = c.take<char>(sb);
+    w.work_bytes = bb;
+    if (ub > w.work_bytes) w.work_bytes = ub;
+    if (pb > w.work_bytes) w.work_bytes = pb;
+    w.work = c.take<char>(w.work_bytes);
+    return BFC_OK;
+}
+
+}  // namespace bfc
+
+extern "C" {
+
+int bfc_spar_batch_filter_ws_size(const bfc_graph *g, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    Carver c(nullptr, 0);
+    FilterWs w;
+    carve_filter(c, g, w);
+    c.take<uint32_t>(1);
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_spar_batch_filter(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
+                          uint64_t *h_kept, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!g || !h_kept || !d_ws) return BFC_E_NULL;
+    BFC_TRY(check_replicas(nrep, reps));
+    if (!aligned256(d_ws)) return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    FilterWs w;
+    carve_filter(c, g, w);
+    uint32_t *last = c.take<uint32_t>(nrep);
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    for (uint32_t i = 0; i < nrep; i++) {
+        FilterArgs f;
+        BFC_TRY(filter_replica(g, reps[i], w, f, s));
+        k_store_last<<<1, 64, 0, s>>>(w.flag, g->n_edges, last + i);
+    }
+    BFC_HIP(hipGetLastError());
+    std::vector<uint32_t> h(nrep);
+    BFC_HIP(hipMemcpyAsync(h.data(), last, nrep * 4, hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < nrep; i++) h_kept[i] = h[i];
+    return BFC_OK;
+}
+
+int bfc_spar_batch_ws_size(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
+                           const uint64_t *h_kept, size_t *bytes) {
+    if (!g || !h_kept || !bytes) return BFC_E_NULL;
+    BFC_TRY(check_replicas(nrep, reps));
+    Carver c(nullptr, 0);
+    BatchWs w;
+    BFC_TRY(carve_batch(c, g, nrep, h_kept, w));
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
+                   const uint64_t *h_kept, const bfc_tuning *tuning, uint64_t *d_beta,
+                   double *d_est, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!g || !h_kept || !d_beta || !d_est || !d_ws) return BFC_E_NULL;
+    BFC_TRY(check_replicas(nrep, reps));
+    if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    BatchWs w;
+    BFC_TRY(carve_batch(c, g, nrep, h_kept, w));
+    if (!c.fits()) return BFC_E_WS_SMALL;
+
+    // 1. kept edges of every replica into the pool, vertices renumbered densely
+    std::vector<uint64_t> eoff(nrep + 1, 0);
+    for (uint32_t i = 0; i < nrep; i++) eoff[i + 1] = eoff[i] + h_kept[i];
+    const unsigned gr = grid_for(g->n_left, 4) > 8192 ? 8192 : grid_for(g->n_left, 4);
+    for (uint32_t i = 0; i < nrep; i++) {
+        FilterArgs f;
+        BFC_TRY(filter_replica(g, reps[i], w.f, f, s));
+        uint32_t *kl = w.kl + eoff[i], *kr = w.kr + eoff[i];
+        const uint64_t mk = h_kept[i];
+        if (g->n_edges) {
+            k_compact<<<gr, 256, 0, s>>>(f, w.f.flag, kl, kr, (uint32_t)mk);
+            k_store_last<<<1, 64, 0, s>>>(w.f.flag, g->n_edges, w.kept_dev + i);
+        } else {
+            k_zero32<<<1, 64, 0, s>>>(w.kept_dev + i, 1);
+        }
+        k_zero32<<<grid_for(g->n_left), 256, 0, s>>>(w.ml, g->n_left);
+        k_zero32<<<grid_for(g->n_right), 256, 0, s>>>(w.mr, g->n_right);
+        if (mk) k_mark_ends<<<grid_for(mk), 256, 0, s>>>(kl, kr, mk, w.ml, w.mr);
+        BFC_HIP(hipGetLastError());
+        if (g->n_left) BFC_TRY(scan_u32_inclusive(w.ml, w.ml, g->n_left, w.scan_tmp_v, s));
+        if (g->n_right) BFC_TRY(scan_u32_inclusive(w.mr, w.mr, g->n_right, w.scan_tmp_v, s));
+        if (mk) k_renumber<<<grid_for(mk), 256, 0, s>>>(kl, kr, mk, w.ml, w.mr);
+        k_store_last<<<1, 64, 0, s>>>(w.ml, g->n_left, w.sizes_dev + 2 * (uint64_t)i);
+        k_store_last<<<1, 64, 0, s>>>(w.mr, g->n_right, w.sizes_dev + 2 * (uint64_t)i + 1);
+        BFC_HIP(hipGetLastError());
+    }
+    std::vector<uint32_t> kept(nrep), sizes(2 * (size_t)nrep);
+    BFC_HIP(hipMemcpyAsync(kept.data(), w.kept_dev, nrep * 4, hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipMemcpyAsync(sizes.data(), w.sizes_dev, sizes.size() * 4, hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < nrep; i++)
+        if (kept[i] != h_kept[i]) return BFC_E_ARG;     // h_kept is not this graph's filter
+
+    // 2. the union (parts oriented by ExactBFC's rule), its CSRs, one count
+    std::vector<uint32_t> nl(nrep), nr(nrep), part_l(nrep + 1), part_r(nrep + 1);
+    std::vector<uint8_t> swapped(nrep);
+    for (uint32_t i = 0; i < nrep; i++) {
+        nl[i] = sizes[2 * (size_t)i];
+        nr[i] = sizes[2 * (size_t)i + 1];
+    }
+    BFC_TRY(bfc_batch_union(nrep, nl.data(), nr.data(), eoff.data(), w.kl, w.kr, w.kl, w.kr,
+                            part_l.data(), part_r.data(), swapped.data(), w.work, w.work_bytes,
+                            s));
+    bfc_graph u;
+    BFC_TRY(bfc_graph_build(part_l[nrep], part_r[nrep], eoff[nrep], w.kl, w.kr, w.storage,
+                            w.storage_bytes, w.work, w.work_bytes, s, &u));
+    BFC_HIP(hipMemcpyAsync(w.part_l, part_l.data(), (nrep + 1) * 4, hipMemcpyHostToDevice, s));
+    BFC_TRY(bfc_exact_parts(&u, nrep, w.part_l, tuning, d_beta, w.work, w.work_bytes, s));
+
+    // 3. estimates, in the single-replica expressions
+    std::vector<double> div(nrep), mul(nrep);
+    for (uint32_t i = 0; i < nrep; i++) {
+        const bfc_replica &r = reps[i];
+        if (r.kind == BFC_REPLICA_ESPAR) {
+            div[i] = (r.p * r.p) * (r.p * r.p);
+            mul[i] = 0.0;
+        } else {
+            const double N = (double)r.ncolors;
+            div[i] = 0.0;
+            mul[i] = N * N * N;
+        }
+    }
+    BFC_HIP(hipMemcpyAsync(w.div, div.data(), nrep * 8, hipMemcpyHostToDevice, s));
+    BFC_HIP(hipMemcpyAsync(w.mul, mul.data(), nrep * 8, hipMemcpyHostToDevice, s));
+    k_est_batch<<<grid_for(nrep), 256, 0, s>>>((const unsigned long long *)d_beta, w.div, w.mul,
+                                               nrep, d_est);
+    BFC_HIP(hipGetLastError());
+    BFC_HIP(hipStreamSynchronize(s));
     return BFC_OK;
 }
 

@@ -37,7 +37,7 @@ import numpy as np
 
 __all__ = ["er", "chung_lu", "capped_expected_degrees", "biclique",
            "disjoint_union", "Workload", "WORKLOADS", "make_workload", "build_native",
-           "mlp_init", "batch_order", "training_graphs"]
+           "mlp_init", "batch_order", "training_graphs", "batch_specs", "batch_graphs"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen_native.c")
@@ -239,4 +239,51 @@ def training_graphs(count: int, m_lo: int, m_hi: int, seed: int, ratio: float = 
         cap = max(2.0, min(100_000.0, 14.0 * math.sqrt(m), nl / 4))
         l, r = chung_lu(nl, nr, m, gamma_l, gamma_r, cap, (seed << 32) | (j + 1))
         out.append((nl, nr, l, r))
+    return out
+
+
+# ---------------------------------------------------------------- batches of uneven graphs
+def batch_specs(count: int, m_lo: int, m_hi: int, seed: int = 3):
+    """Parameters of a batch of uneven graphs (no edges drawn yet).
+
+    Per graph q (one numpy stream seeded with ``seed``): m log-uniform in
+    [m_lo, m_hi]; |L|:|R| = rho uniform in [0.2, 5]; mean degree 2m / (|L| +
+    |R|) log-uniform in [4, 32]; |L| = round(n rho / (1 + rho)), with |L| |R|
+    >= 4m enforced; the first half of the graphs Erdos-Renyi, the second half
+    Chung-Lu with one gamma uniform in [2.0, 2.8] for both sides and the
+    expected-degree cap min(100k, sqrt(|L| |R|)) raised where needed to
+    exceed m / min(|L|, |R|).  Graph q draws its edges with seed
+    (seed << 32) | q.
+    """
+    rng = np.random.default_rng(seed)
+    specs = []
+    for q in range(count):
+        m = int(round(math.exp(rng.uniform(math.log(m_lo), math.log(m_hi)))))
+        rho = rng.uniform(0.2, 5.0)
+        d = math.exp(rng.uniform(math.log(4), math.log(32)))
+        gamma = rng.uniform(2.0, 2.8)
+        n = 2.0 * m / d
+        nl = max(2, int(round(n * rho / (1 + rho))))
+        nr = max(2, int(round(n - nl)))
+        while nl * nr < 4 * m:
+            nl += max(1, nl // 8)
+            nr += max(1, nr // 8)
+        kind = "er" if q < count // 2 else "chung_lu"
+        cap = min(100_000.0, math.sqrt(nl * nr))
+        cap = max(cap, 1.01 * m / min(nl, nr), 2.0)
+        specs.append(dict(q=q, kind=kind, nl=nl, nr=nr, m=m, gamma=gamma, cap=cap,
+                          seed=(seed << 32) | q))
+    return specs
+
+
+def batch_graphs(count: int, m_lo: int, m_hi: int, seed: int = 3):
+    """The graphs of ``batch_specs``: a list of (nl, nr, l, r)."""
+    out = []
+    for sp in batch_specs(count, m_lo, m_hi, seed):
+        if sp["kind"] == "er":
+            l, r = er(sp["nl"], sp["nr"], sp["m"], sp["seed"])
+        else:
+            l, r = chung_lu(sp["nl"], sp["nr"], sp["m"], sp["gamma"], sp["gamma"], sp["cap"],
+                            sp["seed"])
+        out.append((sp["nl"], sp["nr"], l, r))
     return out
