@@ -94,6 +94,17 @@ int bfc_graph_build(uint32_t n_left, uint32_t n_right, uint64_t n_edges,
                     const uint32_t *d_l, const uint32_t *d_r,
                     void *d_storage, size_t storage_bytes,
                     void *d_ws, size_t ws_bytes, hipStream_t stream, bfc_graph *out);
+/* The same for a disjoint union of nparts graphs whose vertices occupy id
+ * ranges: part q owns the L ids [d_part_l[q], d_part_l[q + 1]) and the R ids
+ * [d_part_r[q], d_part_r[q + 1]) (device, nparts + 1 uint32 each, from 0 to
+ * n_left / n_right).  Vertices are ranked by (part, degree, id), another
+ * strict total order, so each part's vertices hold consecutive ranks and a
+ * start's counter windows stay inside its own part.  Same workspace sizes. */
+int bfc_graph_build_parts(uint32_t n_left, uint32_t n_right, uint64_t n_edges,
+                          const uint32_t *d_l, const uint32_t *d_r, uint32_t nparts,
+                          const uint32_t *d_part_l, const uint32_t *d_part_r,
+                          void *d_storage, size_t storage_bytes,
+                          void *d_ws, size_t ws_bytes, hipStream_t stream, bfc_graph *out);
 
 /* ---------------------------------------------------------------------- */
 /* Exact count, ExactBFC (Sec. 4, Lemma 1 Eq. (3)/(4), Lemma 2).            */
@@ -265,18 +276,25 @@ typedef struct bfc_replica {
     double p;           /* ESpar: keep probability, 0 < p <= 1 */
     uint64_t seed;
 } bfc_replica;
-/* Phase 1 (synchronous): kept edges of each replica into h_kept (host, nrep). */
-int bfc_spar_batch_filter_ws_size(const bfc_graph *g, size_t *bytes);
+/* What phase 1 learns of each replica's kept graph (host). */
+typedef struct bfc_replica_info {
+    uint64_t kept;                        /* kept edges */
+    uint32_t n_left, n_right;             /* vertices with a kept edge, per side */
+    uint64_t sumsq_left, sumsq_right;     /* sums of squared kept degrees */
+} bfc_replica_info;
+/* Phase 1 (synchronous): h_info (host, nrep) for every replica. */
+int bfc_spar_batch_filter_ws_size(const bfc_graph *g, uint32_t nrep, size_t *bytes);
 int bfc_spar_batch_filter(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
-                          uint64_t *h_kept, void *d_ws, size_t ws_bytes, hipStream_t stream);
-/* Phase 2 (synchronous): the batch itself; h_kept must be phase 1's output
- * for the same graph and replicas (else BFC_E_ARG).  d_beta (nrep uint64) and
- * d_est (nrep double) are device arrays.  BFC_E_TOO_LARGE when the union
- * would exceed 32-bit ids. */
+                          bfc_replica_info *h_info, void *d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+/* Phase 2 (synchronous): the batch itself, its workspace sized exactly from
+ * h_info, which must be phase 1's output for the same graph and replicas
+ * (else BFC_E_ARG).  d_beta (nrep uint64) and d_est (nrep double) are device
+ * arrays.  BFC_E_TOO_LARGE when the union would exceed 32-bit ids. */
 int bfc_spar_batch_ws_size(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
-                           const uint64_t *h_kept, size_t *bytes);
+                           const bfc_replica_info *h_info, size_t *bytes);
 int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
-                   const uint64_t *h_kept, const bfc_tuning *tuning, uint64_t *d_beta,
+                   const bfc_replica_info *h_info, const bfc_tuning *tuning, uint64_t *d_beta,
                    double *d_est, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------- */

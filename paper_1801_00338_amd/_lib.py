@@ -53,6 +53,11 @@ class bfc_replica(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class bfc_replica_info(C.Structure):
+    _fields_ = [("kept", C.c_uint64), ("n_left", C.c_uint32), ("n_right", C.c_uint32),
+                ("sumsq_left", C.c_uint64), ("sumsq_right", C.c_uint64)]
+
+
 class BfcError(RuntimeError):
     def __init__(self, code, what=""):
         name = ERROR_NAMES.get(code, str(code))
@@ -72,6 +77,9 @@ SIGNATURES = {
     "bfc_graph_build": ([C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p,
                          C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p,
                          C.POINTER(bfc_graph)], C.c_int),
+    "bfc_graph_build_parts": ([C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p,
+                               C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                               C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(bfc_graph)], C.c_int),
     "bfc_side_used": ([C.POINTER(bfc_graph), C.c_int], C.c_int),
     "bfc_wedges": ([C.POINTER(bfc_graph), C.c_int, u64p], C.c_int),
     "bfc_exact_ws_size": ([C.POINTER(bfc_graph), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
@@ -112,12 +120,15 @@ SIGNATURES = {
     "bfc_batch_union": ([C.c_uint32, u32p, u32p, u64p, C.c_void_p, C.c_void_p, C.c_void_p,
                          C.c_void_p, u32p, u32p, C.POINTER(C.c_uint8), C.c_void_p, C.c_size_t,
                          C.c_void_p], C.c_int),
-    "bfc_spar_batch_filter_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
-    "bfc_spar_batch_filter": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica), u64p,
-                               C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
-    "bfc_spar_batch_ws_size": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica), u64p,
-                                C.POINTER(C.c_size_t)], C.c_int),
-    "bfc_spar_batch": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica), u64p,
+    "bfc_spar_batch_filter_ws_size": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(C.c_size_t)],
+                                      C.c_int),
+    "bfc_spar_batch_filter": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica),
+                               C.POINTER(bfc_replica_info), C.c_void_p, C.c_size_t, C.c_void_p],
+                              C.c_int),
+    "bfc_spar_batch_ws_size": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica),
+                                C.POINTER(bfc_replica_info), C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_spar_batch": ([C.POINTER(bfc_graph), C.c_uint32, C.POINTER(bfc_replica),
+                        C.POINTER(bfc_replica_info),
                         C.POINTER(bfc_tuning), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                         C.c_void_p], C.c_int),
     "bfc_mlp_param_count": ([], C.c_int),

@@ -40,7 +40,8 @@ def to_device_u32(a, device="cuda"):
 class Graph:
     """A bipartite graph resident in device memory (both CSRs, rank order)."""
 
-    def __init__(self, n_left, n_right, l, r, device="cuda", stream=None):
+    def __init__(self, n_left, n_right, l, r, device="cuda", stream=None, parts=None):
+        """``parts`` = (part_l, part_r) device uint32 offsets: rank by (part, degree, id)."""
         L = lib()
         self.device = torch.device(device)
         dl = to_device_u32(l, self.device)
@@ -54,10 +55,21 @@ class Graph:
         check(L.bfc_graph_build_ws_size(n_left, n_right, m, C.byref(sz)), "build ws size")
         ws = _bytes(sz.value, self.device)
         self.g = _lib.bfc_graph()
-        check(L.bfc_graph_build(n_left, n_right, m, C.c_void_p(dl.data_ptr()),
-                                C.c_void_p(dr.data_ptr()), C.c_void_p(self.storage.data_ptr()),
-                                self.storage.numel(), C.c_void_p(ws.data_ptr()), ws.numel(),
-                                _stream(stream), C.byref(self.g)), "graph build")
+        if parts is None:
+            check(L.bfc_graph_build(n_left, n_right, m, C.c_void_p(dl.data_ptr()),
+                                    C.c_void_p(dr.data_ptr()),
+                                    C.c_void_p(self.storage.data_ptr()), self.storage.numel(),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                                    C.byref(self.g)), "graph build")
+        else:
+            pl, pr = parts
+            check(L.bfc_graph_build_parts(n_left, n_right, m, C.c_void_p(dl.data_ptr()),
+                                          C.c_void_p(dr.data_ptr()), pl.numel() - 1,
+                                          C.c_void_p(pl.data_ptr()), C.c_void_p(pr.data_ptr()),
+                                          C.c_void_p(self.storage.data_ptr()),
+                                          self.storage.numel(), C.c_void_p(ws.data_ptr()),
+                                          ws.numel(), _stream(stream), C.byref(self.g)),
+                  "graph build (parts)")
         del ws
         self.n_left, self.n_right, self.n_edges = n_left, n_right, m
         self._ws = None
@@ -216,10 +228,12 @@ class Graph:
         """Fastest launch shape for this graph: (bfc_tuning, milliseconds)."""
         return _autotune(self, 0, None)
 
-    def spar_batch(self, replicas, tuning=None):
+    def spar_batch(self, replicas, tuning=None, log=None):
         """Replicas [(kind, param, seed)] with kind "espar" (param p) or "clrspar" (param N),
-        counted in one batch: (counts uint64[n], estimates float64[n], kept edges uint64[n])."""
+        counted in one batch: (counts uint64[n], estimates float64[n], kept edges uint64[n]).
+        ``log`` (optional) receives a line after each phase."""
         L = lib()
+        log = log or (lambda msg: None)
         n = len(replicas)
         reps = (_lib.bfc_replica * n)()
         for i, (kind, param, seed) in enumerate(replicas):
@@ -230,22 +244,29 @@ class Graph:
             else:
                 raise ValueError(kind)
         sz = C.c_size_t()
-        check(L.bfc_spar_batch_filter_ws_size(C.byref(self.g), C.byref(sz)), "filter ws size")
+        check(L.bfc_spar_batch_filter_ws_size(C.byref(self.g), n, C.byref(sz)), "filter ws size")
         ws = _bytes(sz.value, self.device)
-        kept = (C.c_uint64 * n)()
-        check(L.bfc_spar_batch_filter(C.byref(self.g), n, reps, kept, C.c_void_p(ws.data_ptr()),
+        info = (_lib.bfc_replica_info * n)()
+        check(L.bfc_spar_batch_filter(C.byref(self.g), n, reps, info, C.c_void_p(ws.data_ptr()),
                                       ws.numel(), _stream()), "batch filter")
         del ws
-        check(L.bfc_spar_batch_ws_size(C.byref(self.g), n, reps, kept, C.byref(sz)),
+        check(L.bfc_spar_batch_ws_size(C.byref(self.g), n, reps, info, C.byref(sz)),
               "batch ws size")
+        self.last_batch_ws_bytes = sz.value
+        starts = sum(info[i].n_right if info[i].sumsq_left < info[i].sumsq_right
+                     else info[i].n_left for i in range(n))
+        log(f"replica filter done: {sum(info[i].kept for i in range(n))} kept edges, "
+            f"{starts} union start vertices, workspace {sz.value / 1e9:.1f} GB")
         ws = _bytes(sz.value, self.device)
+        kept = [info[i].kept for i in range(n)]
         beta = torch.zeros(n, dtype=torch.int64, device=self.device)
         est = torch.zeros(n, dtype=torch.float64, device=self.device)
         t = _tuning(tuning)
-        check(L.bfc_spar_batch(C.byref(self.g), n, reps, kept, C.byref(t) if t else None,
+        check(L.bfc_spar_batch(C.byref(self.g), n, reps, info, C.byref(t) if t else None,
                                C.c_void_p(beta.data_ptr()), C.c_void_p(est.data_ptr()),
                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "spar batch")
         torch.cuda.synchronize(self.device)
+        log("replica batch counted")
         return (beta.cpu().numpy().view(np.uint64).copy(), est.cpu().numpy().copy(),
                 np.array(kept[:], dtype=np.uint64))
 
@@ -322,9 +343,11 @@ class Batch:
         self.n_graphs = ng
         self.part_l_host, self.part_r_host = part_l, part_r
         self.swapped = swapped[:ng].astype(bool)
-        self.graph = Graph(int(part_l[-1]), int(part_r[-1]), ul[:m], ur[:m], device=self.device)
-        del ul, ur
         self.part_l = to_device_u32(part_l, self.device)
+        self.part_r = to_device_u32(part_r, self.device)
+        self.graph = Graph(int(part_l[-1]), int(part_r[-1]), ul[:m], ur[:m], device=self.device,
+                           parts=(self.part_l, self.part_r) if ng > 0 else None)
+        del ul, ur
         check(L.bfc_exact_parts_ws_size(C.byref(self.graph.g), C.byref(sz)), "parts ws size")
         self.ws = _bytes(sz.value, self.device)
 

@@ -92,7 +92,8 @@ __global__ void k_seg_flags(const uint32_t *adjB, uint64_t m, uint32_t *flag) {
 }
 
 __global__ void k_seg_rowstarts(const uint32_t *offB, uint32_t nB, uint32_t *flag) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nB; v += gridDim.x * blockDim.x)
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < nB;
+         v += (uint64_t)gridDim.x * blockDim.x)
         if (offB[v] < offB[v + 1]) flag[offB[v]] = 1u;
 }
 
@@ -175,22 +176,27 @@ __global__ __launch_bounds__(256) void k_scatter_items(const uint8_t *bucket, ui
                                                        QueueState *q, uint32_t *items,
                                                        uint32_t *items_wide) {
     __shared__ uint32_t hist[2][NBUCKET], base[2][NBUCKET];
-    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
-    __syncthreads();
-    uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t b = 0, cls = 0, local = 0;
-    if (u < nA) {
-        b = bucket[u] & 127u;
-        cls = bucket[u] >> 7;
-        if (b) local = atomicAdd(&hist[cls][b], 1u);
+    // blocks stride over chunks of blockDim.x starts (the grid is capped)
+    for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x; c0 < nA;
+         c0 += (uint64_t)gridDim.x * blockDim.x) {
+        for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
+        __syncthreads();
+        const uint64_t u = c0 + threadIdx.x;
+        uint32_t b = 0, cls = 0, local = 0;
+        if (u < nA) {
+            b = bucket[u] & 127u;
+            cls = bucket[u] >> 7;
+            if (b) local = atomicAdd(&hist[cls][b], 1u);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) {
+            uint32_t h = (&hist[0][0])[i];
+            if (h) (&base[0][0])[i] = atomicAdd(&(&q->cursor[0][0])[i], h);
+        }
+        __syncthreads();
+        if (b) (cls ? items_wide : items)[base[cls][b] + local] = (uint32_t)u;
+        __syncthreads();            // hist and base are reset for the next chunk
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) {
-        uint32_t h = (&hist[0][0])[i];
-        if (h) (&base[0][0])[i] = atomicAdd(&(&q->cursor[0][0])[i], h);
-    }
-    __syncthreads();
-    if (b) (cls ? items_wide : items)[base[cls][b] + local] = u;
 }
 
 __global__ void k_zero_u32(uint32_t *p, uint64_t n) {
@@ -826,7 +832,8 @@ __global__ __launch_bounds__(256) void k_part_sums(const unsigned long long *per
 // B_v of the midpoint side from the edge sums; outputs in caller ids.
 __global__ void k_local_finish(const unsigned long long *twiceB, const uint32_t *idB, uint32_t nB,
                                unsigned long long *cntB) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nB; v += gridDim.x * blockDim.x)
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < nB;
+         v += (uint64_t)gridDim.x * blockDim.x)
         cntB[idB[v]] = twiceB[v] >> 1;
 }
 

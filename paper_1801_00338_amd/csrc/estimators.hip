@@ -121,7 +121,8 @@ __global__ __launch_bounds__(256) void k_compact(FilterArgs f, const uint32_t *s
 }
 
 __global__ void k_colours(uint32_t n, uint32_t side, uint32_t N, uint64_t seed, uint32_t *col) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x)
         col[v] = colour_of(seed, side, v, N);
 }
 
@@ -532,10 +533,50 @@ __global__ void k_zero32(uint32_t *p, uint64_t n) {
 
 __global__ void k_est_batch(const unsigned long long *beta, const double *div, const double *mul,
                             uint32_t n, double *est) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
         const double b = (double)beta[i];
         est[i] = div[i] != 0.0 ? b / div[i] : b * mul[i];
     }
+}
+
+// Degrees of the kept edges (flags from k_filter), by ids.
+__global__ __launch_bounds__(256) void k_kept_degrees(FilterArgs f, const uint32_t *flag,
+                                                      uint32_t *deg_l, uint32_t *deg_r) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
+    for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < f.nl; u += gridDim.x * wpb) {
+        const uint32_t l = f.id_l[u];
+        for (uint32_t k = f.off_l[u] + lane; k < f.off_l[u + 1]; k += WAVE)
+            if (flag[k]) {
+                atomicAdd(&deg_l[l], 1u);
+                atomicAdd(&deg_r[f.id_r[f.adj_l[k]]], 1u);
+            }
+    }
+}
+
+// out[0] += vertices of nonzero degree, out[1] += sum of squared degrees.
+__global__ __launch_bounds__(256) void k_deg_stats(const uint32_t *deg, uint64_t n,
+                                                   unsigned long long *out) {
+    __shared__ unsigned long long red[256 / WAVE];
+    unsigned long long c = 0, q = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long d = deg[i];
+        c += d != 0;
+        q += d * d;
+    }
+    c = block_sum64<256>(c, red);
+    q = block_sum64<256>(q, red);
+    if (threadIdx.x == 0) {
+        if (c) atomicAdd(&out[0], c);
+        if (q) atomicAdd(&out[1], q);
+    }
+}
+
+__global__ void k_zero64(unsigned long long *p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 static int check_replicas(uint32_t nrep, const bfc_replica *reps) {
@@ -604,7 +645,7 @@ static int filter_replica(const bfc_graph *g, const bfc_replica &rep, FilterWs &
 
 struct BatchWs {
     FilterWs f;
-    uint32_t *ml, *mr, *scan_tmp_v, *kl, *kr, *kept_dev, *sizes_dev, *part_l;
+    uint32_t *ml, *mr, *scan_tmp_v, *kl, *kr, *kept_dev, *sizes_dev, *part_l, *part_r;
     double *div, *mul;
     void *storage;
     size_t storage_bytes;
@@ -612,25 +653,34 @@ struct BatchWs {
     size_t work_bytes;
 };
 
-// Bounds of the union: part i has at most min(n, kept_i) vertices per side,
-// and either side may become the union's L.
-static int batch_bounds(const bfc_graph *g, uint32_t nrep, const uint64_t *h_kept, uint64_t &M,
-                        uint64_t &NV) {
-    M = NV = 0;
+// Sizes of the union: edges, vertices of each union side (each part enters
+// with its start side as L: ExactBFC's rule on its own degrees), and the
+// sums of the parts' vertex counts before orientation.
+struct BatchSizes {
+    uint64_t M, NL, NR, SL, SR;
+};
+
+static int batch_sizes(uint32_t nrep, const bfc_replica_info *info, BatchSizes &z) {
+    z = BatchSizes{0, 0, 0, 0, 0};
     for (uint32_t i = 0; i < nrep; i++) {
-        const uint64_t k = h_kept[i];
-        const uint64_t a = k < g->n_left ? k : g->n_left, b = k < g->n_right ? k : g->n_right;
-        M += k;
-        NV += a > b ? a : b;
+        const bfc_replica_info &r = info[i];
+        const bool sw = r.sumsq_left < r.sumsq_right;
+        z.M += r.kept;
+        z.NL += sw ? r.n_right : r.n_left;
+        z.NR += sw ? r.n_left : r.n_right;
+        z.SL += r.n_left;
+        z.SR += r.n_right;
     }
-    if (M > 0xFFFFFFFFull - ADJ_SLACK || NV > 0xFFFFFFFEull) return BFC_E_TOO_LARGE;
+    if (z.M > 0xFFFFFFFFull - ADJ_SLACK || z.NL > 0xFFFFFFFEull || z.NR > 0xFFFFFFFEull)
+        return BFC_E_TOO_LARGE;
     return BFC_OK;
 }
 
-static int carve_batch(Carver &c, const bfc_graph *g, uint32_t nrep, const uint64_t *h_kept,
+static int carve_batch(Carver &c, const bfc_graph *g, uint32_t nrep, const bfc_replica_info *info,
                        BatchWs &w) {
-    uint64_t M, NV;
-    BFC_TRY(batch_bounds(g, nrep, h_kept, M, NV));
+    BatchSizes z;
+    BFC_TRY(batch_sizes(nrep, info, z));
+    const uint64_t M = z.M;
     carve_filter(c, g, w.f);
     const uint64_t nv = (uint64_t)g->n_left > g->n_right ? g->n_left : g->n_right;
     w.ml = c.take<uint32_t>(pad64(g->n_left));
@@ -641,17 +691,18 @@ static int carve_batch(Carver &c, const bfc_graph *g, uint32_t nrep, const uint6
     w.kept_dev = c.take<uint32_t>(nrep);
     w.sizes_dev = c.take<uint32_t>(2 * (uint64_t)nrep);
     w.part_l = c.take<uint32_t>(nrep + 1);
+    w.part_r = c.take<uint32_t>(nrep + 1);
     w.div = c.take<double>(nrep);
     w.mul = c.take<double>(nrep);
     size_t sb, bb, ub, pb;
-    BFC_TRY(bfc_graph_storage_size((uint32_t)NV, (uint32_t)NV, M, &sb));
-    BFC_TRY(bfc_graph_build_ws_size((uint32_t)NV, (uint32_t)NV, M, &bb));
+    BFC_TRY(bfc_graph_storage_size((uint32_t)z.NL, (uint32_t)z.NR, M, &sb));
+    BFC_TRY(bfc_graph_build_ws_size((uint32_t)z.NL, (uint32_t)z.NR, M, &bb));
     // union workspace: offsets per part plus degree slots for both sides
     {
         Carver u(nullptr, 0);
         u.take<uint64_t>(3 * ((uint64_t)nrep + 1));
-        u.take<uint32_t>(pad64(NV));
-        u.take<uint32_t>(pad64(NV));
+        u.take<uint32_t>(pad64(z.SL));
+        u.take<uint32_t>(pad64(z.SR));
         u.take<uint32_t>(3 * ((uint64_t)nrep + 1));
         u.take<uint8_t>(nrep + 1);
         u.take<unsigned long long>(2 * (uint64_t)nrep);
@@ -660,8 +711,8 @@ static int carve_batch(Carver &c, const bfc_graph *g, uint32_t nrep, const uint6
     {
         // bfc_exact_parts on a graph of these sizes, counted from L
         Carver e(nullptr, 0);
-        e.take<char>(exact_ws_bound((uint32_t)NV, (uint32_t)NV, M));
-        e.take<unsigned long long>(pad64(NV));
+        e.take<char>(exact_ws_bound((uint32_t)z.NL, (uint32_t)z.NR, M));
+        e.take<unsigned long long>(pad64(z.NL > z.NR ? z.NL : z.NR));
         e.take<unsigned long long>(1);
         pb = e.used;
     }
@@ -678,60 +729,89 @@ static int carve_batch(Carver &c, const bfc_graph *g, uint32_t nrep, const uint6
 
 extern "C" {
 
-int bfc_spar_batch_filter_ws_size(const bfc_graph *g, size_t *bytes) {
+int bfc_spar_batch_filter_ws_size(const bfc_graph *g, uint32_t nrep, size_t *bytes) {
     if (!g || !bytes) return BFC_E_NULL;
     Carver c(nullptr, 0);
     FilterWs w;
     carve_filter(c, g, w);
-    c.take<uint32_t>(1);
+    c.take<uint32_t>(pad64(g->n_left));
+    c.take<uint32_t>(pad64(g->n_right));
+    c.take<unsigned long long>(5 * (uint64_t)nrep);
     *bytes = c.used;
     return BFC_OK;
 }
 
 int bfc_spar_batch_filter(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
-                          uint64_t *h_kept, void *d_ws, size_t ws_bytes, hipStream_t s) {
-    if (!g || !h_kept || !d_ws) return BFC_E_NULL;
+                          bfc_replica_info *h_info, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!g || !h_info || !d_ws) return BFC_E_NULL;
     BFC_TRY(check_replicas(nrep, reps));
     if (!aligned256(d_ws)) return BFC_E_ALIGN;
     Carver c(d_ws, ws_bytes);
     FilterWs w;
     carve_filter(c, g, w);
-    uint32_t *last = c.take<uint32_t>(nrep);
+    uint32_t *deg_l = c.take<uint32_t>(pad64(g->n_left));
+    uint32_t *deg_r = c.take<uint32_t>(pad64(g->n_right));
+    unsigned long long *st = c.take<unsigned long long>(5 * (uint64_t)nrep);
     if (!c.fits()) return BFC_E_WS_SMALL;
+    k_zero64<<<grid_for(5 * (uint64_t)nrep), 256, 0, s>>>(st, 5 * (uint64_t)nrep);
+    unsigned gr = grid_for(g->n_left, 4);
+    if (gr > 8192) gr = 8192;
+    unsigned gl = grid_for(g->n_left), gR = grid_for(g->n_right);
+    if (gl > 4096) gl = 4096;
+    if (gR > 4096) gR = 4096;
     for (uint32_t i = 0; i < nrep; i++) {
         FilterArgs f;
         BFC_TRY(filter_replica(g, reps[i], w, f, s));
-        k_store_last<<<1, 64, 0, s>>>(w.flag, g->n_edges, last + i);
+        unsigned long long *o = st + 5 * (uint64_t)i;
+        k_store_last<<<1, 64, 0, s>>>(w.flag, g->n_edges, (uint32_t *)(o + 4));
+        // the scan left the flags as running counts: recompute the flags for the degrees
+        k_zero32<<<grid_for(g->n_left), 256, 0, s>>>(deg_l, g->n_left);
+        k_zero32<<<grid_for(g->n_right), 256, 0, s>>>(deg_r, g->n_right);
+        if (g->n_edges) {
+            k_filter<<<gr, 256, 0, s>>>(f, w.flag);
+            k_kept_degrees<<<gr, 256, 0, s>>>(f, w.flag, deg_l, deg_r);
+        }
+        if (g->n_left) k_deg_stats<<<gl, 256, 0, s>>>(deg_l, g->n_left, o);
+        if (g->n_right) k_deg_stats<<<gR, 256, 0, s>>>(deg_r, g->n_right, o + 2);
+        BFC_HIP(hipGetLastError());
     }
-    BFC_HIP(hipGetLastError());
-    std::vector<uint32_t> h(nrep);
-    BFC_HIP(hipMemcpyAsync(h.data(), last, nrep * 4, hipMemcpyDeviceToHost, s));
+    std::vector<unsigned long long> h(5 * (size_t)nrep);
+    BFC_HIP(hipMemcpyAsync(h.data(), st, h.size() * 8, hipMemcpyDeviceToHost, s));
     BFC_HIP(hipStreamSynchronize(s));
-    for (uint32_t i = 0; i < nrep; i++) h_kept[i] = h[i];
+    for (uint32_t i = 0; i < nrep; i++) {
+        const unsigned long long *o = &h[5 * (size_t)i];
+        h_info[i].kept = (uint32_t)o[4];
+        h_info[i].n_left = (uint32_t)o[0];
+        h_info[i].sumsq_left = o[1];
+        h_info[i].n_right = (uint32_t)o[2];
+        h_info[i].sumsq_right = o[3];
+    }
     return BFC_OK;
 }
 
 int bfc_spar_batch_ws_size(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
-                           const uint64_t *h_kept, size_t *bytes) {
-    if (!g || !h_kept || !bytes) return BFC_E_NULL;
+                           const bfc_replica_info *h_info, size_t *bytes) {
+    if (!g || !h_info || !bytes) return BFC_E_NULL;
     BFC_TRY(check_replicas(nrep, reps));
     Carver c(nullptr, 0);
     BatchWs w;
-    BFC_TRY(carve_batch(c, g, nrep, h_kept, w));
+    BFC_TRY(carve_batch(c, g, nrep, h_info, w));
     *bytes = c.used;
     return BFC_OK;
 }
 
 int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
-                   const uint64_t *h_kept, const bfc_tuning *tuning, uint64_t *d_beta,
+                   const bfc_replica_info *h_info, const bfc_tuning *tuning, uint64_t *d_beta,
                    double *d_est, void *d_ws, size_t ws_bytes, hipStream_t s) {
-    if (!g || !h_kept || !d_beta || !d_est || !d_ws) return BFC_E_NULL;
+    if (!g || !h_info || !d_beta || !d_est || !d_ws) return BFC_E_NULL;
     BFC_TRY(check_replicas(nrep, reps));
     if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
     Carver c(d_ws, ws_bytes);
     BatchWs w;
-    BFC_TRY(carve_batch(c, g, nrep, h_kept, w));
+    BFC_TRY(carve_batch(c, g, nrep, h_info, w));
     if (!c.fits()) return BFC_E_WS_SMALL;
+    std::vector<uint64_t> h_kept(nrep);
+    for (uint32_t i = 0; i < nrep; i++) h_kept[i] = h_info[i].kept;
 
     // 1. kept edges of every replica into the pool, vertices renumbered densely
     std::vector<uint64_t> eoff(nrep + 1, 0);
@@ -763,8 +843,10 @@ int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
     BFC_HIP(hipMemcpyAsync(kept.data(), w.kept_dev, nrep * 4, hipMemcpyDeviceToHost, s));
     BFC_HIP(hipMemcpyAsync(sizes.data(), w.sizes_dev, sizes.size() * 4, hipMemcpyDeviceToHost, s));
     BFC_HIP(hipStreamSynchronize(s));
-    for (uint32_t i = 0; i < nrep; i++)
-        if (kept[i] != h_kept[i]) return BFC_E_ARG;     // h_kept is not this graph's filter
+    for (uint32_t i = 0; i < nrep; i++)        // h_info must be this graph's phase 1
+        if (kept[i] != h_kept[i] || sizes[2 * (size_t)i] != h_info[i].n_left ||
+            sizes[2 * (size_t)i + 1] != h_info[i].n_right)
+            return BFC_E_ARG;
 
     // 2. the union (parts oriented by ExactBFC's rule), its CSRs, one count
     std::vector<uint32_t> nl(nrep), nr(nrep), part_l(nrep + 1), part_r(nrep + 1);
@@ -777,9 +859,11 @@ int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
                             part_l.data(), part_r.data(), swapped.data(), w.work, w.work_bytes,
                             s));
     bfc_graph u;
-    BFC_TRY(bfc_graph_build(part_l[nrep], part_r[nrep], eoff[nrep], w.kl, w.kr, w.storage,
-                            w.storage_bytes, w.work, w.work_bytes, s, &u));
     BFC_HIP(hipMemcpyAsync(w.part_l, part_l.data(), (nrep + 1) * 4, hipMemcpyHostToDevice, s));
+    BFC_HIP(hipMemcpyAsync(w.part_r, part_r.data(), (nrep + 1) * 4, hipMemcpyHostToDevice, s));
+    BFC_TRY(bfc_graph_build_parts(part_l[nrep], part_r[nrep], eoff[nrep], w.kl, w.kr, nrep,
+                                  w.part_l, w.part_r, w.storage, w.storage_bytes, w.work,
+                                  w.work_bytes, s, &u));
     BFC_TRY(bfc_exact_parts(&u, nrep, w.part_l, tuning, d_beta, w.work, w.work_bytes, s));
 
     // 3. estimates, in the single-replica expressions

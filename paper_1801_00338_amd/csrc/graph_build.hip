@@ -126,15 +126,38 @@ __global__ void k_degrees(const uint32_t *l, const uint32_t *r, uint64_t m, uint
 }
 
 __global__ void k_iota(uint32_t *p, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = i;
+}
+
+// Keys (part, degree) for a part-major rank order: part q owns the ids
+// [part[q], part[q + 1]).
+__global__ void k_part_keys(const uint32_t *deg, uint32_t n, const uint32_t *part, uint32_t np,
+                            unsigned long long *keys) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = np;               // last q with part[q] <= i
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (part[mid] <= i) lo = mid; else hi = mid;
+        }
+        keys[i] = ((unsigned long long)lo << 32) | deg[i];
+    }
+}
+
+__global__ void k_low_words(const unsigned long long *keys, uint32_t n, uint32_t *low) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        low[i] = (uint32_t)keys[i];
 }
 
 // After sorting (degree, id) pairs: rank[id_sorted[i]] = i; the sorted
 // degrees become the row lengths in rank order (copied into off[1..n]).
 __global__ void k_ranks(const uint32_t *ids_sorted, const uint32_t *deg_sorted, uint32_t n,
                         uint32_t *rank, uint32_t *row_len) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
         rank[ids_sorted[i]] = i;
         row_len[i] = deg_sorted[i];
     }
@@ -145,7 +168,8 @@ __global__ void k_degree_stats(const uint32_t *deg, uint32_t n, unsigned long lo
     __shared__ unsigned long long red[256 / WAVE];
     unsigned long long s = 0, w = 0;
     uint32_t mx = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
         unsigned long long d = deg[i];
         s += d * d;
         w += d * (d - (d > 0)) / 2;
@@ -246,9 +270,10 @@ struct BuildWs {
 static size_t sort_tmp_needed(uint32_t nl, uint32_t nr, uint64_t m) {
     size_t a = 0, b = 0;
     uint64_t nmax = nl > nr ? nl : nr;
+    const uint64_t big = m > nmax ? m : nmax;
     (void)rocprim::radix_sort_pairs(nullptr, a, (unsigned long long *)nullptr,
                               (unsigned long long *)nullptr, (uint32_t *)nullptr,
-                              (uint32_t *)nullptr, (size_t)(m ? m : 1), 0, 64);
+                              (uint32_t *)nullptr, (size_t)(big ? big : 1), 0, 64);
     (void)rocprim::radix_sort_pairs(nullptr, b, (uint32_t *)nullptr, (uint32_t *)nullptr,
                               (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)(nmax ? nmax : 1),
                               0, 32);
@@ -264,8 +289,9 @@ static BuildWs carve_ws(Carver &c, uint32_t nl, uint32_t nr, uint64_t m) {
     w.deg_sorted = c.take<uint32_t>(pad64(nmax));
     w.ids_in = c.take<uint32_t>(pad64(nmax));
     w.ids_out = c.take<uint32_t>(pad64(nmax));
-    w.keys_in = c.take<unsigned long long>(pad64(m));
-    w.keys_out = c.take<unsigned long long>(pad64(m));
+    const uint64_t big = m > nmax ? m : nmax;   // edge keys, or vertex keys of a part-major rank
+    w.keys_in = c.take<unsigned long long>(pad64(big));
+    w.keys_out = c.take<unsigned long long>(pad64(big));
     w.vals_in = c.take<uint32_t>(pad64(m));
     w.vals_out = c.take<uint32_t>(pad64(m));
     w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(nmax + 1));
@@ -281,9 +307,11 @@ static int check_sizes(uint32_t nl, uint32_t nr, uint64_t m) {
     return BFC_OK;
 }
 
-// Rank one side by (degree, id) and build its row offsets.
+// Rank one side by (degree, id), or by (part, degree, id) when part offsets
+// are given, and build its row offsets.
 static int rank_side(uint32_t n, const uint32_t *deg, BuildWs &w, uint32_t *rank, uint32_t *id,
-                     uint32_t *off, hipStream_t s) {
+                     uint32_t *off, hipStream_t s, const uint32_t *part = nullptr,
+                     uint32_t nparts = 0) {
     if (n == 0) {
         k_fill_u32<<<1, 64, 0, s>>>(off, 1, 0);
         BFC_HIP(hipGetLastError());
@@ -291,8 +319,17 @@ static int rank_side(uint32_t n, const uint32_t *deg, BuildWs &w, uint32_t *rank
     }
     k_iota<<<grid_for(n), 256, 0, s>>>(w.ids_in, n);
     size_t tb = w.sort_tmp_bytes;
-    BFC_HIP(rocprim::radix_sort_pairs(w.sort_tmp, tb, deg, w.deg_sorted, w.ids_in, id, (size_t)n,
-                                      0, 32, s));
+    if (part && nparts > 1) {
+        k_part_keys<<<grid_for(n), 256, 0, s>>>(deg, n, part, nparts, w.keys_in);
+        BFC_HIP(hipGetLastError());
+        const int hb = 32 + bits_for(nparts);
+        BFC_HIP(rocprim::radix_sort_pairs(w.sort_tmp, tb, w.keys_in, w.keys_out, w.ids_in, id,
+                                          (size_t)n, 0, hb, s));
+        k_low_words<<<grid_for(n), 256, 0, s>>>(w.keys_out, n, w.deg_sorted);
+    } else {
+        BFC_HIP(rocprim::radix_sort_pairs(w.sort_tmp, tb, deg, w.deg_sorted, w.ids_in, id,
+                                          (size_t)n, 0, 32, s));
+    }
     k_fill_u32<<<1, 64, 0, s>>>(off, 1, 0);
     k_ranks<<<grid_for(n), 256, 0, s>>>(id, w.deg_sorted, n, rank, off + 1);
     BFC_HIP(hipGetLastError());
@@ -359,9 +396,10 @@ int bfc_graph_build_ws_size(uint32_t nl, uint32_t nr, uint64_t m, size_t *bytes)
     return BFC_OK;
 }
 
-int bfc_graph_build(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *d_l,
-                    const uint32_t *d_r, void *d_storage, size_t storage_bytes, void *d_ws,
-                    size_t ws_bytes, hipStream_t s, bfc_graph *out) {
+static int build_graph(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *d_l,
+                       const uint32_t *d_r, uint32_t nparts, const uint32_t *part_l,
+                       const uint32_t *part_r, void *d_storage, size_t storage_bytes, void *d_ws,
+                       size_t ws_bytes, hipStream_t s, bfc_graph *out) {
     if (!out || !d_storage || !d_ws || (m && (!d_l || !d_r))) return BFC_E_NULL;
     BFC_TRY(check_sizes(nl, nr, m));
     if (!aligned256(d_storage) || !aligned256(d_ws)) return BFC_E_ALIGN;
@@ -398,8 +436,8 @@ int bfc_graph_build(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *d_l,
                                                      &w.flags->max_deg_r);
     }
     BFC_HIP(hipGetLastError());
-    BFC_TRY(rank_side(nl, w.deg_l, w, L.rank_l, L.id_l, L.off_l, s));
-    BFC_TRY(rank_side(nr, w.deg_r, w, L.rank_r, L.id_r, L.off_r, s));
+    BFC_TRY(rank_side(nl, w.deg_l, w, L.rank_l, L.id_l, L.off_l, s, part_l, nparts));
+    BFC_TRY(rank_side(nr, w.deg_r, w, L.rank_r, L.id_r, L.off_r, s, part_r, nparts));
     BFC_TRY(build_csr(d_l, d_r, m, nr, L.rank_l, L.rank_r, nl, w, L.adj_l, L.eid_l, s));
     BFC_TRY(build_csr(d_r, d_l, m, nl, L.rank_r, L.rank_l, nr, w, L.adj_r, L.eid_r, s));
     if (m) {
@@ -432,6 +470,23 @@ int bfc_graph_build(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *d_l,
     g.device = dev;
     *out = g;
     return BFC_OK;
+}
+
+int bfc_graph_build(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *d_l,
+                    const uint32_t *d_r, void *d_storage, size_t storage_bytes, void *d_ws,
+                    size_t ws_bytes, hipStream_t s, bfc_graph *out) {
+    return build_graph(nl, nr, m, d_l, d_r, 0, nullptr, nullptr, d_storage, storage_bytes, d_ws,
+                       ws_bytes, s, out);
+}
+
+int bfc_graph_build_parts(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *d_l,
+                          const uint32_t *d_r, uint32_t nparts, const uint32_t *d_part_l,
+                          const uint32_t *d_part_r, void *d_storage, size_t storage_bytes,
+                          void *d_ws, size_t ws_bytes, hipStream_t s, bfc_graph *out) {
+    if (nparts == 0) return BFC_E_ARG;
+    if (!d_part_l || !d_part_r) return BFC_E_NULL;
+    return build_graph(nl, nr, m, d_l, d_r, nparts, d_part_l, d_part_r, d_storage, storage_bytes,
+                       d_ws, ws_bytes, s, out);
 }
 
 }  // extern "C"

@@ -209,3 +209,44 @@ def test_full_batch_1024_graphs(env):
         nl, nr, l, r = graphs[q]
         assert int(got[q]) == api.Graph(nl, nr, l, r).exact(), q
     print(f"batch checks done in {time.time() - t1:.1f} s", flush=True)
+
+
+def test_full_replica_batch_256(env):
+    """256 replicas of the 10M/30M/100M-edge graph in one batch: 128 ESpar (32
+    each at p = 0.01, 0.02, 0.05, 0.1) and 128 ClrSpar (32 each at N = 4, 8,
+    16, 32), replica r seeded (4 << 32) | r.  Sampled replicas equal the
+    oracle and the single-replica calls bit for bit; every group's mean
+    estimate lies within four standard errors of the exact count."""
+    torch, api = env
+    w = gen.WORKLOADS["chung_lu_10m_30m_100m"]
+    t0 = time.time()
+    l, r = w.edges()
+    print(f"generated {w.name} in {time.time() - t0:.1f} s", flush=True)
+    g = api.Graph(w.nl, w.nr, l, r)
+    B = g.exact()
+    print(f"graph built and counted: B={B}", flush=True)
+    reps = []
+    for p in (0.01, 0.02, 0.05, 0.1):
+        reps += [("espar", p, (4 << 32) | len(reps) + i) for i in range(32)]
+    for n in (4, 8, 16, 32):
+        reps += [("clrspar", n, (4 << 32) | len(reps) + i) for i in range(32)]
+    t0 = time.time()
+    beta, est, kept = g.spar_batch(reps, log=lambda msg: print(msg, flush=True))
+    print(f"B={B}; batch of {len(reps)} replicas, {int(kept.sum())} kept edges, workspace "
+          f"{g.last_batch_ws_bytes / 1e9:.1f} GB, {time.time() - t0:.1f} s", flush=True)
+    for grp in range(8):
+        e = est[32 * grp:32 * grp + 32]
+        kind, param, _ = reps[32 * grp]
+        se = e.std(ddof=1) / math.sqrt(32)
+        print(f"{kind} {param}: mean {e.mean():.6g} rel.err {(e.mean() - B) / B:+.4f} "
+              f"std {e.std(ddof=1):.4g}", flush=True)
+        assert abs(e.mean() - B) <= 4 * se + 1e-9 * B, (kind, param)
+    # sampled replicas: the oracle on the cheapest, single GPU calls on others
+    for i in (0, 32 * 7 + 5):
+        kind, param, sd = reps[i]
+        want = (oracle.espar if kind == "espar" else oracle.clrspar)(w.nl, w.nr, l, r, param, sd)
+        assert (int(beta[i]), float(est[i]), int(kept[i])) == want, (kind, param, sd)
+    for i in (32 * 3 + 1, 32 * 4 + 2):
+        kind, param, sd = reps[i]
+        single = g.espar(param, sd) if kind == "espar" else g.clrspar(param, sd)
+        assert (int(beta[i]), float(est[i]), int(kept[i])) == single, (kind, param, sd)
