@@ -200,6 +200,26 @@ class Graph:
         ids_np = ids_np.view(np.uint32) if id_dtype == torch.int32 else ids_np.view(np.uint64)
         return ids_np[:k].copy(), cnt.cpu().numpy().view(np.uint64)[:k].copy(), float(est.item())
 
+    def vsamp_buffers(self, k):
+        """Device buffers for vsamp_async with k draws."""
+        L = lib()
+        sz = C.c_size_t()
+        check(L.bfc_vsamp_ws_size(C.byref(self.g), k, C.byref(sz)), "vsamp ws size")
+        return dict(ws=_bytes(sz.value, self.device), k=k,
+                    ids=torch.zeros(max(k, 1), dtype=torch.int32, device=self.device),
+                    cnt=torch.zeros(max(k, 1), dtype=torch.int64, device=self.device),
+                    est=torch.zeros(1, dtype=torch.float64, device=self.device))
+
+    def vsamp_async(self, buf, seed, probs=None, stream=None):
+        """Queue VSamp with buf["k"] draws; probs a float64 device tensor or None."""
+        ws = buf["ws"]
+        check(lib().bfc_vsamp(C.byref(self.g),
+                              C.c_void_p(probs.data_ptr()) if probs is not None else None,
+                              buf["k"], seed, C.c_void_p(buf["ids"].data_ptr()),
+                              C.c_void_p(buf["cnt"].data_ptr()), C.c_void_p(buf["est"].data_ptr()),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "vsamp")
+        return buf["est"]
+
     def vsamp(self, k, seed, probs=None):
         """VSamp: (drawn global ids, their counts, estimate)."""
         L = lib()

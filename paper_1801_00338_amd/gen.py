@@ -182,6 +182,9 @@ WORKLOADS = {
     "chung_lu_10m_30m_100m": Workload("chung_lu_10m_30m_100m", "chung_lu",
                                       10_000_000, 30_000_000, 100_000_000,
                                       2.2, 2.4, 100_000, seed=4),
+    "chung_lu_20m_80m_400m": Workload("chung_lu_20m_80m_400m", "chung_lu",
+                                      20_000_000, 80_000_000, 400_000_000,
+                                      2.1, 2.3, 100_000, seed=5),
 }
 
 
