@@ -596,9 +596,11 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
 // keeps each midpoint's sub-run of the window to read the final counts back
 // in a second pass.
 constexpr int NWAVES = NT / WT;
+constexpr int TBL_WORDS_L = 1 << 14;   // local counts: 64 KiB table, two workgroups per CU
 
-struct Shared {
-    uint32_t tbl[TBL_WORDS + NT];       // counters, then one zero word per thread
+template <int TW>
+struct SharedT {
+    uint32_t tbl[TW + NT];              // counters, then one zero word per thread
     uint32_t pre[NWAVES][WT], lo[NWAVES][WT], hi[NWAVES][WT], skip[NWAVES][WT];
     unsigned long long esum[NWAVES][WT];
     uint32_t red[NWAVES + 1];
@@ -606,9 +608,10 @@ struct Shared {
     uint32_t item;
 };
 
-__device__ inline void clear_table(Shared &sh) {
+template <int TW>
+__device__ inline void clear_table(SharedT<TW> &sh) {
     const uint4 z = make_uint4(0, 0, 0, 0);
-    for (int i = threadIdx.x; i < TBL_WORDS / 4; i += NT) ((uint4 *)sh.tbl)[i] = z;
+    for (int i = threadIdx.x; i < TW / 4; i += NT) ((uint4 *)sh.tbl)[i] = z;
 }
 
 // Order this wave's LDS writes before its later reads (no other wave involved).
@@ -618,7 +621,8 @@ __device__ inline void wave_sync() {
 }
 
 // Piece pi of this wave's chunk (prefix over the chunk's 64 midpoints).
-__device__ inline Piece cpiece(const Shared &sh, uint32_t wv, uint32_t pi, bool valid) {
+template <int TW>
+__device__ inline Piece cpiece(const SharedT<TW> &sh, uint32_t wv, uint32_t pi, bool valid) {
     uint32_t j = 0;
 #pragma unroll
     for (uint32_t s = WT / 2; s; s >>= 1) j = sh.pre[wv][j + s - 1] <= pi ? j + s : j;
@@ -637,10 +641,12 @@ __device__ inline Piece cpiece(const Shared &sh, uint32_t wv, uint32_t pi, bool 
 }
 
 // pass 0: add one to the counters of the piece's entries, return the sum of
-// previous values; pass 1: return the sum of the final counters.
-__device__ inline uint32_t cpiece_walk(Shared &sh, int pass, const Piece &pc, const uint4 *q,
-                                       uint32_t wb) {
-    const uint32_t zw = TBL_WORDS + threadIdx.x;
+// previous values; pass 1: return the sum of the final counters.  HALF: two
+// 16-bit counters per word (C_u[w] <= d_u <= 65535), else 32-bit counters.
+template <int TW, int HALF>
+__device__ inline uint32_t cpiece_walk(SharedT<TW> &sh, int pass, const Piece &pc,
+                                       const uint4 *q, uint32_t wb) {
+    const uint32_t zw = TW + threadIdx.x;
     uint32_t v[4 * WK];
 #pragma unroll
     for (int k = 0; k < WK; k++) {
@@ -649,8 +655,17 @@ __device__ inline uint32_t cpiece_walk(Shared &sh, int pass, const Piece &pc, co
         for (int i = 0; i < 4; i++) {
             const uint32_t pos = pc.base + 4 * k + i;
             const bool on = (pos - pc.lo) < pc.len && pos != pc.skip;
-            const uint32_t idx = on ? w[i] - wb : zw;
-            v[4 * k + i] = pass == 0 ? atomicAdd(&sh.tbl[idx], (uint32_t)on) : sh.tbl[idx];
+            const uint32_t rel = w[i] - wb;
+            if (HALF) {
+                const uint32_t word = on ? rel >> 1 : zw;
+                const uint32_t sft = (rel & 1u) << 4;
+                const uint32_t x = pass == 0 ? atomicAdd(&sh.tbl[word], (uint32_t)on << sft)
+                                             : sh.tbl[word];
+                v[4 * k + i] = (x >> sft) & 0xFFFFu;
+            } else {
+                const uint32_t idx = on ? rel : zw;
+                v[4 * k + i] = pass == 0 ? atomicAdd(&sh.tbl[idx], (uint32_t)on) : sh.tbl[idx];
+            }
         }
     }
     uint32_t s = 0;
@@ -660,7 +675,8 @@ __device__ inline uint32_t cpiece_walk(Shared &sh, int pass, const Piece &pc, co
 }
 
 // One chunk of 64 midpoints (this wave): publish the sub-runs, walk pieces.
-__device__ inline void chunk_walk(const CountArgs &a, Shared &sh, int pass, uint32_t lo,
+template <int TW, int HALF>
+__device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass, uint32_t lo,
                                   uint32_t hi, uint32_t skip, uint32_t wb,
                                   unsigned long long &sum, unsigned long long &esum_mid) {
     const uint32_t lane = threadIdx.x & (WT - 1), wv = threadIdx.x / WT;
@@ -680,7 +696,7 @@ __device__ inline void chunk_walk(const CountArgs &a, Shared &sh, int pass, uint
         const Piece pc = cpiece(sh, wv, pi < NP ? pi : 0, pi < NP);
         uint4 q[WK];
         wfetch<WK>(a.adjB, pc, q);
-        const uint32_t s = cpiece_walk(sh, pass, pc, q, wb);
+        const uint32_t s = cpiece_walk<TW, HALF>(sh, pass, pc, q, wb);
         if (pass == 0) part += s;
         else if (s) atomicAdd(&sh.esum[wv][pc.j], (unsigned long long)s);
     }
@@ -690,9 +706,13 @@ __device__ inline void chunk_walk(const CountArgs &a, Shared &sh, int pass, uint
     wave_sync();
 }
 
-template <bool LOCAL>
-__device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t rb, uint32_t du,
-                                        const WideScratch &ws, bool pass2) {
+// A table window covers 2^LOGW consecutive segment windows (2^(G_SHIFT +
+// LOGW) ranks); each midpoint's sub-run of a table window is the union of
+// its (contiguous) segments there, at most 2^LOGW of them.
+template <bool LOCAL, int TW, int HALF, int LOGW>
+__device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uint32_t rb,
+                                        uint32_t du, const WideScratch &ws, bool pass2) {
+    static_assert((HALF ? 2 : 1) * TW == (1 << (G_SHIFT + LOGW)), "table covers one window");
     const uint32_t tid = threadIdx.x, lane = tid & (WT - 1), wv = tid / WT;
     unsigned long long sum = 0;
     uint32_t mn = INF;
@@ -703,7 +723,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t
         uint32_t p = LOCAL ? pb : a.xA[k] + 1, s = 0;
         if (LOCAL ? (ev - pb > 1) : (p < ev)) {
             s = a.seg1[p] - 1;
-            mn = min(mn, a.seg_win[s]);
+            mn = min(mn, a.seg_win[s] >> LOGW);
         } else {
             p = ev;                             // nothing to walk
         }
@@ -713,7 +733,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t
     }
     uint32_t kw = block_min<NT>(mn, sh.red);
     while (kw != INF) {
-        const uint32_t wb = kw << G_SHIFT;
+        const uint32_t wb = kw << (G_SHIFT + LOGW);
         uint32_t next = INF;
         for (uint32_t cb = wv * WT; cb < du; cb += NT) {
             const uint32_t j = cb + lane, k = rb + j;
@@ -721,16 +741,20 @@ __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t
             if (j < du) {
                 const uint32_t ev = a.offB[a.adjA[k] + 1];
                 uint32_t p = ws.pos[k], s = ws.seg[k];
-                if (p < ev && a.seg_win[s] == kw) {
+                if (p < ev && (a.seg_win[s] >> LOGW) == kw) {
                     lo = p;
-                    const uint32_t e = a.seg_start[s + 1];
+                    uint32_t e = a.seg_start[s + 1];
+                    s++;
+                    while (e < ev && (a.seg_win[s] >> LOGW) == kw) {
+                        e = a.seg_start[s + 1];
+                        s++;
+                    }
                     hi = e < ev ? e : ev;
                     p = hi;
-                    s++;
                     ws.pos[k] = p;
                     ws.seg[k] = s;
                 }
-                if (p < ev) next = min(next, a.seg_win[s]);
+                if (p < ev) next = min(next, a.seg_win[s] >> LOGW);
                 if (LOCAL) {
                     skip = a.xA[k];
                     ws.lo[k] = lo;
@@ -738,7 +762,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t
                 }
             }
             unsigned long long unused;
-            chunk_walk(a, sh, 0, lo, hi, skip, wb, sum, unused);
+            chunk_walk<TW, HALF>(a, sh, 0, lo, hi, skip, wb, sum, unused);
         }
         if (LOCAL && pass2) {
             __syncthreads();                    // all counts of the window are final
@@ -751,7 +775,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t
                     skip = a.xA[k];
                 }
                 unsigned long long e = 0;
-                chunk_walk(a, sh, 1, lo, hi, skip, wb, sum, e);
+                chunk_walk<TW, HALF>(a, sh, 1, lo, hi, skip, wb, sum, e);
                 if (j < du && e) ws.esum[k] += e;
             }
         }
@@ -762,7 +786,8 @@ __device__ unsigned long long walk_wide(const CountArgs &a, Shared &sh, uint32_t
     return sum;
 }
 
-__device__ inline uint32_t block_take(Shared &sh, QueueState *q) {
+template <int TW>
+__device__ inline uint32_t block_take(SharedT<TW> &sh, QueueState *q) {
     __syncthreads();
     if (threadIdx.x == 0) sh.item = atomicAdd(&q->head[1], 1u);
     __syncthreads();
@@ -770,7 +795,7 @@ __device__ inline uint32_t block_take(Shared &sh, QueueState *q) {
 }
 
 __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) {
-    __shared__ Shared sh;
+    __shared__ SharedT<TBL_WORDS> sh;
     clear_table(sh);
     sh.tbl[TBL_WORDS + threadIdx.x] = 0;
     const uint32_t n = a.q->n_items[1];
@@ -778,7 +803,8 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
     for (uint32_t it = block_take(sh, a.q); it < n; it = block_take(sh, a.q)) {
         const uint32_t u = a.items_wide[it];
         const uint32_t rb = a.offA[u];
-        const unsigned long long s = walk_wide<false>(a, sh, rb, a.offA[u + 1] - rb, ws, false);
+        const unsigned long long s =
+            walk_wide<false, TBL_WORDS, 0, 0>(a, sh, rb, a.offA[u + 1] - rb, ws, false);
         if (a.per_start) {
             const unsigned long long t = block_sum64<NT>(s, sh.red64);
             if (threadIdx.x == 0) a.per_start[u] = t;
@@ -789,16 +815,21 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
     finish_launch(a.q, 1, acc, a.total);
 }
 
+// Local counts of wide starts: 16-bit counters over windows of 2^15 ranks
+// when d_u <= 65535 (two segment windows per table), else 32-bit counters
+// over 2^14.
 __global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a, WideScratch ws) {
-    __shared__ Shared sh;
+    __shared__ SharedT<TBL_WORDS_L> sh;
     clear_table(sh);
-    sh.tbl[TBL_WORDS + threadIdx.x] = 0;
+    sh.tbl[TBL_WORDS_L + threadIdx.x] = 0;
     const uint32_t n = a.c.q->n_items[1];
     const uint32_t tid = threadIdx.x;
     for (uint32_t it = block_take(sh, a.c.q); it < n; it = block_take(sh, a.c.q)) {
         const uint32_t u = a.c.items_wide[it];
         const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
-        unsigned long long s = walk_wide<true>(a.c, sh, rb, du, ws, a.pass2);
+        unsigned long long s =
+            du <= 0xFFFFu ? walk_wide<true, TBL_WORDS_L, 1, 1>(a.c, sh, rb, du, ws, a.pass2)
+                          : walk_wide<true, TBL_WORDS_L, 0, 0>(a.c, sh, rb, du, ws, a.pass2);
         __syncthreads();
         if (a.pass2) {
             for (uint32_t j = tid; j < du; j += NT) {

@@ -134,3 +134,36 @@ def test_dense_windows_multi_round(api):
     l = np.repeat(np.arange(nl, dtype=np.uint32), 50)
     r = np.concatenate([rng.choice(nr, 50, replace=False) for _ in range(nl)]).astype(np.uint32)
     check_all(api, nl, nr, l, r)
+
+
+def test_local_wide_table_modes(api):
+    """Local counts of wide starts in both table modes: 16-bit counters over
+    2^15-rank windows (255 < d_u <= 65535) and 32-bit counters over 2^14
+    ranks (d_u > 65535), with starts spread over several table windows."""
+    rng = np.random.default_rng(23)
+    nl, nr = 150_000, 70_000
+    parts_l, parts_r = [], []
+    # hub L0 joined to every R vertex (degree 70,000 > 65,535)
+    parts_l.append(np.zeros(nr, np.uint32))
+    parts_r.append(np.arange(nr, dtype=np.uint32))
+    # 40 L vertices of degree 300..5000 (the 16-bit mode), spread over the id range
+    for i, d in enumerate(np.linspace(300, 5000, 40).astype(int)):
+        parts_l.append(np.full(d, 1 + i * 3000, np.uint32))
+        parts_r.append(rng.choice(nr, d, replace=False).astype(np.uint32))
+    l = np.concatenate(parts_l)
+    r = np.concatenate(parts_r)
+    # sparse background: random edges among the other L vertices
+    bl = rng.integers(1, nl, 200_000).astype(np.uint32)
+    br = rng.integers(0, nr, 200_000).astype(np.uint32)
+    key = np.unique(np.concatenate([l.astype(np.uint64) * nr + r,
+                                    bl.astype(np.uint64) * nr + br]))
+    l = (key // nr).astype(np.uint32)
+    r = (key % nr).astype(np.uint32)
+    g = api.Graph(nl, nr, l, r)
+    assert g.side_used() == api.BFC_SIDE_L and g.max_degree[0] == nr
+    print(f"case nl={nl} nr={nr} m={l.size}", flush=True)
+    cl, cr, ce = g.local()
+    ol, orr = oracle.per_vertex(nl, nr, l, r)
+    assert np.array_equal(cl, ol) and np.array_equal(cr, orr)
+    assert np.array_equal(ce, oracle.per_edge(nl, nr, l, r))
+    assert g.exact() == oracle.exact(nl, nr, l, r)[0]
