@@ -297,6 +297,7 @@ struct WShared {
     uint32_t tbl[WTBL_WORDS + WT];      // byte counters, then one zero word per lane
     uint32_t pre[WSLOTS * WT];          // exclusive prefix of pieces per midpoint
     uint32_t lo[WSLOTS * WT], hi[WSLOTS * WT];
+    uint32_t own[WT];                   // 1 + midpoint of piece i (windows of <= 64 pieces)
     uint32_t skip[LOCAL ? WSLOTS * WT : 1];
     unsigned long long esum[LOCAL ? WSLOTS * WT : 1];
 };
@@ -320,6 +321,31 @@ __device__ inline Piece wpiece(const WShared<LOCAL> &sh, uint32_t du, uint32_t p
     Piece pc;
     const uint32_t lo = sh.lo[j], hi = sh.hi[j];
     const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * WK;
+    const uint32_t end = min(hi, (g0 + WK) << 2);
+    pc.base = valid ? g0 << 2 : 0;
+    pc.lo = lo;
+    pc.len = valid ? end - lo : 0;
+    pc.skip = LOCAL ? sh.skip[j] : INF;
+    pc.j = j;
+    return pc;
+}
+
+// Piece `lane` of a window with at most one piece per lane: the owner
+// table holds 1 + midpoint at each midpoint's first piece; a wave max-scan
+// carries it over that midpoint's other pieces (midpoints and their first
+// pieces increase together).
+template <bool LOCAL>
+__device__ inline Piece wpiece_direct(const WShared<LOCAL> &sh, uint32_t lane, bool valid) {
+    uint32_t o = sh.own[lane];
+#pragma unroll
+    for (int d = 1; d < WT; d <<= 1) {
+        const uint32_t t = __shfl_up(o, d, WT);
+        if (lane >= (uint32_t)d) o = max(o, t);
+    }
+    const uint32_t j = (o ? o : 1u) - 1;
+    Piece pc;
+    const uint32_t lo = sh.lo[j], hi = sh.hi[j];
+    const uint32_t g0 = (lo >> 2) + (lane - sh.pre[j]) * WK;
     const uint32_t end = min(hi, (g0 + WK) << 2);
     pc.base = valid ? g0 << 2 : 0;
     pc.lo = lo;
@@ -452,6 +478,9 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
         if (kw == INF) break;
         // sub-runs of this window and the prefix sums of their pieces
         uint32_t run = 0;
+        uint32_t first[WSLOTS], cnt[WSLOTS];
+#pragma unroll
+        for (int s = 0; s < WSLOTS; s++) first[s] = cnt[s] = 0;
 #pragma unroll
         for (int s = 0; s < WSLOTS; s++) {
             if (s >= (int)ns) break;
@@ -478,16 +507,25 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             sh.pre[j] = run + inc - np;
             sh.lo[j] = lo;
             sh.hi[j] = hi;
+            first[s] = run + inc - np;
+            cnt[s] = np;
             run += __shfl(inc, WT - 1, WT);
         }
         const uint32_t NP = run;
+        if (NP <= (uint32_t)WT) {
+            sh.own[lane] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < WSLOTS; s++)
+                if (cnt[s]) sh.own[first[s]] = lane + s * WT + 1;
+        }
         __syncthreads();
         const uint32_t wb = kw << G_SHIFT;
         uint32_t part = 0;
         if (NP <= (uint32_t)WT) {
             // one piece per lane: keep it in registers for the second look
             // and the clear
-            const Piece pc = wpiece(sh, du, lane, lane < NP);
+            const Piece pc = wpiece_direct(sh, lane, lane < NP);
             uint4 q[WK];
             wfetch<WK>(a.adjB, pc, q);
             part = wbump(sh, pc, q, wb);
