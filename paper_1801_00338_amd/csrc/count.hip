@@ -342,7 +342,7 @@ __device__ inline Piece wpiece_direct(const WShared<LOCAL> &sh, uint32_t lane, b
         const uint32_t t = __shfl_up(o, d, WT);
         if (lane >= (uint32_t)d) o = max(o, t);
     }
-    const uint32_t j = (o ? o : 1u) - 1;
+    const uint32_t j = min((o ? o : 1u) - 1, (uint32_t)(WSLOTS * WT - 1));
     Piece pc;
     const uint32_t lo = sh.lo[j], hi = sh.hi[j];
     const uint32_t g0 = (lo >> 2) + (lane - sh.pre[j]) * WK;
@@ -469,14 +469,16 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             sh.esum[j] = 0;
         }
     }
-    unsigned long long sum = 0;
-    for (;;) {
+    // Advance every slot past the current window, publish the sub-runs of
+    // the next window touched (kw, INF when none), their piece prefix and,
+    // for a window of at most one piece per lane, the owner table; returns
+    // the number of pieces.
+    auto next_window = [&](uint32_t &kw) -> uint32_t {
         uint32_t mn = INF;
 #pragma unroll
         for (int s = 0; s < WSLOTS; s++) mn = min(mn, win[s]);
-        const uint32_t kw = wave_min(mn);
-        if (kw == INF) break;
-        // sub-runs of this window and the prefix sums of their pieces
+        kw = wave_min(mn);
+        if (kw == INF) return 0u;
         uint32_t run = 0;
         uint32_t first[WSLOTS], cnt[WSLOTS];
 #pragma unroll
@@ -511,56 +513,104 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             cnt[s] = np;
             run += __shfl(inc, WT - 1, WT);
         }
-        const uint32_t NP = run;
-        if (NP <= (uint32_t)WT) {
+        if (run <= (uint32_t)WT) {
             sh.own[lane] = 0;
             __syncthreads();
 #pragma unroll
             for (int s = 0; s < WSLOTS; s++)
                 if (cnt[s]) sh.own[first[s]] = lane + s * WT + 1;
         }
-        __syncthreads();
-        const uint32_t wb = kw << G_SHIFT;
-        uint32_t part = 0;
-        if (NP <= (uint32_t)WT) {
-            // one piece per lane: keep it in registers for the second look
-            // and the clear
-            const Piece pc = wpiece_direct(sh, lane, lane < NP);
-            uint4 q[WK];
-            wfetch<WK>(a.adjB, pc, q);
-            part = wbump(sh, pc, q, wb);
-            if (LOCAL && pass2) {
-                __syncthreads();
-                const uint32_t v = wread(sh, pc, q, wb);
-                if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
-            }
+        return run;
+    };
+
+    // Bump, second look and clear of one window held in registers.
+    auto finish = [&](const Piece &pc, const uint4 *q, uint32_t wb) -> uint32_t {
+        const uint32_t part = wbump(sh, pc, q, wb);
+        if (LOCAL && pass2) {
             __syncthreads();
-            wclear(sh, pc, q, wb);
-        } else {
+            const uint32_t v = wread(sh, pc, q, wb);
+            if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
+        }
+        __syncthreads();
+        wclear(sh, pc, q, wb);
+        __syncthreads();
+        return part;
+    };
+
+    // Windows of at most one piece per lane run as a two-stage pipeline: the
+    // pieces of the next window are loaded while the current window's
+    // counters are bumped and cleared.  The loop is unrolled twice so that
+    // the two register buffers swap roles without a copy (a copy would wait
+    // for the loads in flight).  A window with more pieces than lanes is
+    // walked in rounds from the published prefixes.
+    unsigned long long sum = 0;
+    uint32_t kw;                        // the published window
+    uint32_t NP = next_window(kw);
+    __syncthreads();
+    Piece pa, pb;
+    uint4 qa[WK], qb[WK];
+    while (kw != INF) {
+        if (NP > (uint32_t)WT) {
+            const uint32_t wb = kw << G_SHIFT;
             const uint32_t rounds = (NP + WT - 1) / WT;
+            uint32_t part = 0;
             for (uint32_t r = 0; r < rounds; r++) {
                 const uint32_t pi = lane + r * WT;
-                const Piece pc = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
-                uint4 q[WK];
-                wfetch<WK>(a.adjB, pc, q);
-                part += wbump(sh, pc, q, wb);
+                const Piece pr = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
+                uint4 qr[WK];
+                wfetch<WK>(a.adjB, pr, qr);
+                part += wbump(sh, pr, qr, wb);
             }
             if (LOCAL && pass2) {
                 __syncthreads();
                 for (uint32_t r = 0; r < rounds; r++) {
                     const uint32_t pi = lane + r * WT;
-                    const Piece pc = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
-                    uint4 q[WK];
-                    wfetch<WK>(a.adjB, pc, q);
-                    const uint32_t v = wread(sh, pc, q, wb);
-                    if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
+                    const Piece pr = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
+                    uint4 qr[WK];
+                    wfetch<WK>(a.adjB, pr, qr);
+                    const uint32_t v = wread(sh, pr, qr, wb);
+                    if (v) atomicAdd(&sh.esum[pr.j], (unsigned long long)v);
                 }
             }
             __syncthreads();
             wclear_all(sh);
+            sum += part;
+            __syncthreads();
+            NP = next_window(kw);
+            __syncthreads();
+            continue;
         }
-        sum += part;
+        // prologue: window kw into (pa, qa), publish the following one
+        pa = wpiece_direct(sh, lane, lane < NP);
+        wfetch<WK>(a.adjB, pa, qa);
+        uint32_t kwa = kw;
         __syncthreads();
+        NP = next_window(kw);
+        __syncthreads();
+        for (;;) {
+            // (pa, qa) hold window kwa; window kw is published
+            // the next window's loads are issued unconditionally (a lane
+            // without a piece reads the first group) so that no branch
+            // joins the buffers while their loads are in flight
+            bool more = kw != INF && NP <= (uint32_t)WT;
+            pb = wpiece_direct(sh, lane, more && lane < NP);
+            wfetch<WK>(a.adjB, pb, qb);
+            sum += finish(pa, qa, kwa << G_SHIFT);
+            if (!more) break;
+            const uint32_t kwb = kw;
+            NP = next_window(kw);
+            __syncthreads();
+            // (pb, qb) hold window kwb; window kw is published
+            more = kw != INF && NP <= (uint32_t)WT;
+            pa = wpiece_direct(sh, lane, more && lane < NP);
+            wfetch<WK>(a.adjB, pa, qa);
+            sum += finish(pb, qb, kwb << G_SHIFT);
+            if (!more) break;
+            kwa = kw;
+            NP = next_window(kw);
+            __syncthreads();
+        }
+        // here window kw (if any) has more pieces than lanes, or none is left
     }
     return sum;
 }
