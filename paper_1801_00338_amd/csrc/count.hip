@@ -486,24 +486,22 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
 #pragma unroll
         for (int s = 0; s < WSLOTS; s++) {
             if (s >= (int)ns) break;
-            uint32_t lo = 0, hi = 0, np = 0;
-            if (win[s] == kw) {
-                lo = p[s];
-                hi = sn[s] < ev[s] ? sn[s] : ev[s];
-                np = (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK;
-                p[s] = hi;
-                if (p[s] < ev[s]) {
-                    cur[s]++;
-                    win[s] = w2[s];
-                    sn[s] = s2[s];
-                    if (sn[s] < ev[s]) {
-                        w2[s] = a.seg_win[cur[s] + 1];
-                        s2[s] = a.seg_start[cur[s] + 2];
-                    }
-                } else {
-                    win[s] = INF;
-                }
-            }
+            // branch-free: the look-ahead loads below must not be merged at
+            // a branch join (that would wait for them here)
+            const bool act = win[s] == kw;
+            const uint32_t h = sn[s] < ev[s] ? sn[s] : ev[s];
+            const uint32_t lo = act ? p[s] : 0u, hi = act ? h : 0u;
+            const uint32_t np = act ? (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK : 0u;
+            const bool adv = act && h < ev[s];
+            p[s] = act ? h : p[s];
+            cur[s] += adv ? 1u : 0u;
+            win[s] = act ? (adv ? w2[s] : INF) : win[s];
+            sn[s] = adv ? s2[s] : sn[s];
+            // look-ahead from the cursor (unchanged values when it did not
+            // move); used from the next window on.  cur + 2 <= segments + 1,
+            // inside the padded segment arrays.
+            w2[s] = a.seg_win[cur[s] + 1];
+            s2[s] = a.seg_start[cur[s] + 2];
             const uint32_t inc = wave_incl_scan(np);
             const uint32_t j = lane + s * WT;
             sh.pre[j] = run + inc - np;
