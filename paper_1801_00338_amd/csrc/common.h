@@ -67,20 +67,53 @@ int scan_u32_inclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *
 // ------------------------------------------------------------------ device helpers
 constexpr int WAVE = 64;
 
+// Wave-wide scans on the DPP paths (register to register, no LDS round
+// trip): a Hillis-Steele scan inside each row of 16 lanes (row_shr 1, 2, 4,
+// 8), then the row totals carried with row_bcast:15 into rows 1 and 3 and
+// row_bcast:31 into rows 2 and 3.  Lanes whose DPP source is outside the
+// row, or rows the row mask leaves out, read the identity.  Call with all
+// 64 lanes active.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ inline uint32_t dpp_u32(uint32_t ident, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, CTRL, ROWS, 0xf, BOUND);
+}
+
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, WAVE);
-        if (lane >= d) v += t;
-    }
+    v += dpp_u32<0x111, 0xf, true>(0u, v);
+    v += dpp_u32<0x112, 0xf, true>(0u, v);
+    v += dpp_u32<0x114, 0xf, true>(0u, v);
+    v += dpp_u32<0x118, 0xf, true>(0u, v);
+    v += dpp_u32<0x142, 0xa, false>(0u, v);
+    v += dpp_u32<0x143, 0xc, false>(0u, v);
     return v;
 }
 
-__device__ inline uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int d = WAVE / 2; d > 0; d >>= 1) v = min(v, (uint32_t)__shfl_xor(v, d, WAVE));
+// Inclusive running maximum (identity 0).
+__device__ inline uint32_t wave_incl_max(uint32_t v) {
+    v = max(v, dpp_u32<0x111, 0xf, true>(0u, v));
+    v = max(v, dpp_u32<0x112, 0xf, true>(0u, v));
+    v = max(v, dpp_u32<0x114, 0xf, true>(0u, v));
+    v = max(v, dpp_u32<0x118, 0xf, true>(0u, v));
+    v = max(v, dpp_u32<0x142, 0xa, false>(0u, v));
+    v = max(v, dpp_u32<0x143, 0xc, false>(0u, v));
     return v;
+}
+
+// Minimum over the wave, returned to every lane (identity 0xFFFFFFFF).
+__device__ inline uint32_t wave_min(uint32_t v) {
+    const uint32_t I = 0xFFFFFFFFu;
+    v = min(v, dpp_u32<0x111, 0xf, false>(I, v));
+    v = min(v, dpp_u32<0x112, 0xf, false>(I, v));
+    v = min(v, dpp_u32<0x114, 0xf, false>(I, v));
+    v = min(v, dpp_u32<0x118, 0xf, false>(I, v));
+    v = min(v, dpp_u32<0x142, 0xa, false>(I, v));
+    v = min(v, dpp_u32<0x143, 0xc, false>(I, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1);
+}
+
+// Value of lane 63 (wave-uniform).
+__device__ inline uint32_t wave_last(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1);
 }
 
 __device__ inline unsigned long long wave_sum64(unsigned long long v) {

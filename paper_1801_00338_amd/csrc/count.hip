@@ -336,12 +336,7 @@ __device__ inline Piece wpiece(const WShared<LOCAL> &sh, uint32_t du, uint32_t p
 // pieces increase together).
 template <bool LOCAL>
 __device__ inline Piece wpiece_direct(const WShared<LOCAL> &sh, uint32_t lane, bool valid) {
-    uint32_t o = sh.own[lane];
-#pragma unroll
-    for (int d = 1; d < WT; d <<= 1) {
-        const uint32_t t = __shfl_up(o, d, WT);
-        if (lane >= (uint32_t)d) o = max(o, t);
-    }
+    const uint32_t o = wave_incl_max(sh.own[lane]);
     const uint32_t j = min((o ? o : 1u) - 1, (uint32_t)(WSLOTS * WT - 1));
     Piece pc;
     const uint32_t lo = sh.lo[j], hi = sh.hi[j];
@@ -509,7 +504,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             sh.hi[j] = hi;
             first[s] = run + inc - np;
             cnt[s] = np;
-            run += __shfl(inc, WT - 1, WT);
+            run += wave_last(inc);
         }
         if (run <= (uint32_t)WT) {
             sh.own[lane] = 0;
@@ -768,7 +763,7 @@ __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass,
     const uint32_t lane = threadIdx.x & (WT - 1), wv = threadIdx.x / WT;
     const uint32_t np = hi > lo ? (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK : 0;
     const uint32_t inc = wave_incl_scan(np);
-    const uint32_t NP = __shfl(inc, WT - 1, WT);
+    const uint32_t NP = wave_last(inc);
     sh.pre[wv][lane] = inc - np;
     sh.lo[wv][lane] = lo;
     sh.hi[wv][lane] = hi;
