@@ -429,6 +429,12 @@ __device__ inline void wclear_all(WShared<LOCAL> &sh) {
 // Walk of one narrow start by one wave.  Lane l owns midpoints l + 64 s.
 // EXACT: endpoints ranked above u.  LOCAL: all endpoints other than u, with
 // the per-midpoint sums of final counts accumulated in sh.esum.
+// Order this wave's LDS writes before its later reads (no other wave involved).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <bool LOCAL>
 __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, uint32_t rb,
                                         uint32_t du, bool pass2) {
@@ -468,6 +474,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
     // the next window touched (kw, INF when none), their piece prefix and,
     // for a window of at most one piece per lane, the owner table; returns
     // the number of pieces.
+    uint32_t first[WSLOTS], cnt[WSLOTS];  // this lane's midpoints: first piece, pieces
     auto next_window = [&](uint32_t &kw) -> uint32_t {
         uint32_t mn = INF;
 #pragma unroll
@@ -475,7 +482,6 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
         kw = wave_min(mn);
         if (kw == INF) return 0u;
         uint32_t run = 0;
-        uint32_t first[WSLOTS], cnt[WSLOTS];
 #pragma unroll
         for (int s = 0; s < WSLOTS; s++) first[s] = cnt[s] = 0;
 #pragma unroll
@@ -544,30 +550,68 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
     uint4 qa[WK], qb[WK];
     while (kw != INF) {
         if (NP > (uint32_t)WT) {
+            // Rounds of 64 pieces.  Round r's pieces are mapped to midpoints
+            // through the owner table (the midpoints whose first piece falls
+            // in the round, plus the one carried over from the round
+            // before), and the next round's pieces are loaded while this
+            // round's counters are bumped (unrolled twice, no copies).
             const uint32_t wb = kw << G_SHIFT;
             const uint32_t rounds = (NP + WT - 1) / WT;
-            uint32_t part = 0;
-            for (uint32_t r = 0; r < rounds; r++) {
-                const uint32_t pi = lane + r * WT;
-                const Piece pr = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
-                uint4 qr[WK];
-                wfetch<WK>(a.adjB, pr, qr);
-                part += wbump(sh, pr, qr, wb);
-            }
-            if (LOCAL && pass2) {
-                __syncthreads();
-                for (uint32_t r = 0; r < rounds; r++) {
-                    const uint32_t pi = lane + r * WT;
-                    const Piece pr = wpiece(sh, du, pi < NP ? pi : 0, pi < NP);
-                    uint4 qr[WK];
-                    wfetch<WK>(a.adjB, pr, qr);
-                    const uint32_t v = wread(sh, pr, qr, wb);
-                    if (v) atomicAdd(&sh.esum[pr.j], (unsigned long long)v);
+            auto map_round = [&](uint32_t r, uint32_t &carry) -> Piece {
+                const uint32_t r0 = r * WT;
+                sh.own[lane] = 0;
+                wave_sync();
+#pragma unroll
+                for (int s = 0; s < WSLOTS; s++)
+                    if (cnt[s] && first[s] - r0 < (uint32_t)WT)
+                        sh.own[first[s] - r0] = lane + s * WT + 1;
+                wave_sync();
+                const uint32_t o = max(wave_incl_max(sh.own[lane]), carry);
+                carry = wave_last(o);
+                const uint32_t j = min((o ? o : 1u) - 1, (uint32_t)(WSLOTS * WT - 1));
+                const uint32_t pi = r0 + lane;
+                const bool valid = pi < NP;
+                Piece pc;
+                const uint32_t lo = sh.lo[j], hi = sh.hi[j];
+                const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * WK;
+                const uint32_t end = min(hi, (g0 + WK) << 2);
+                pc.base = valid ? g0 << 2 : 0;
+                pc.lo = lo;
+                pc.len = valid ? end - lo : 0;
+                pc.skip = LOCAL ? sh.skip[j] : INF;
+                pc.j = j;
+                return pc;
+            };
+            // pass 0 bumps the counters, pass 1 reads the final counts
+            for (int pass = 0; pass < ((LOCAL && pass2) ? 2 : 1); pass++) {
+                uint32_t carry = 0, part = 0;
+                Piece r0p = map_round(0, carry);
+                uint4 q0[WK], q1[WK];
+                wfetch<WK>(a.adjB, r0p, q0);
+                for (uint32_t r = 0;; r += 2) {
+                    Piece r1p = map_round(r + 1, carry);
+                    wfetch<WK>(a.adjB, r1p, q1);
+                    if (pass == 0) {
+                        part += wbump(sh, r0p, q0, wb);
+                    } else {
+                        const uint32_t v = wread(sh, r0p, q0, wb);
+                        if (v) atomicAdd(&sh.esum[r0p.j], (unsigned long long)v);
+                    }
+                    if (r + 1 >= rounds) break;
+                    r0p = map_round(r + 2, carry);
+                    wfetch<WK>(a.adjB, r0p, q0);
+                    if (pass == 0) {
+                        part += wbump(sh, r1p, q1, wb);
+                    } else {
+                        const uint32_t v = wread(sh, r1p, q1, wb);
+                        if (v) atomicAdd(&sh.esum[r1p.j], (unsigned long long)v);
+                    }
+                    if (r + 2 >= rounds) break;
                 }
+                sum += part;
+                __syncthreads();            // every count of the window is final
             }
-            __syncthreads();
             wclear_all(sh);
-            sum += part;
             __syncthreads();
             NP = next_window(kw);
             __syncthreads();
@@ -695,11 +739,6 @@ __device__ inline void clear_table(SharedT<TW> &sh) {
     for (int i = threadIdx.x; i < TW / 4; i += NT) ((uint4 *)sh.tbl)[i] = z;
 }
 
-// Order this wave's LDS writes before its later reads (no other wave involved).
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 // Piece pi of this wave's chunk (prefix over the chunk's 64 midpoints).
 template <int TW>
