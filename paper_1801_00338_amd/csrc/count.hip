@@ -923,8 +923,11 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
     for (uint32_t it = block_take(sh, a.q); it < n; it = block_take(sh, a.q)) {
         const uint32_t u = a.items_wide[it];
         const uint32_t rb = a.offA[u];
+        const uint32_t du = a.offA[u + 1] - rb;
+        // 16-bit counters over two segment windows when C_u[w] <= d_u fits
         const unsigned long long s =
-            walk_wide<false, TBL_WORDS, 0, 0>(a, sh, rb, a.offA[u + 1] - rb, ws, false);
+            du <= 0xFFFFu ? walk_wide<false, TBL_WORDS, 1, 1>(a, sh, rb, du, ws, false)
+                          : walk_wide<false, TBL_WORDS, 0, 0>(a, sh, rb, du, ws, false);
         if (a.per_start) {
             const unsigned long long t = block_sum64<NT>(s, sh.red64);
             if (threadIdx.x == 0) a.per_start[u] = t;
