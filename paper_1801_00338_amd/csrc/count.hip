@@ -262,6 +262,7 @@ struct LocalArgs {
 // Per-midpoint state of wide starts, one slot per A-side adjacency position.
 struct WideScratch {
     uint32_t *pos, *seg;          // cursor: next position and its segment
+    uint32_t *lim, *sw, *se;      // list end; window and end of the cursor's segment
     uint32_t *lo, *hi;            // sub-run of the current window (local counts)
     unsigned long long *esum;     // sums of final counts (local counts)
 };
@@ -840,15 +841,20 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
         const uint32_t k = rb + j;
         const uint32_t v = a.adjA[k];
         const uint32_t pb = a.offB[v], ev = a.offB[v + 1];
-        uint32_t p = LOCAL ? pb : a.xA[k] + 1, s = 0;
+        uint32_t p = LOCAL ? pb : a.xA[k] + 1, s = 0, sw = INF, se = 0;
         if (LOCAL ? (ev - pb > 1) : (p < ev)) {
             s = a.seg1[p] - 1;
-            mn = min(mn, a.seg_win[s] >> LOGW);
+            sw = a.seg_win[s];
+            se = a.seg_start[s + 1];
+            mn = min(mn, sw >> LOGW);
         } else {
             p = ev;                             // nothing to walk
         }
         ws.pos[k] = p;
         ws.seg[k] = s;
+        ws.lim[k] = ev;
+        ws.sw[k] = sw;
+        ws.se[k] = se;
         if (LOCAL) ws.esum[k] = 0;
     }
     uint32_t kw = block_min<NT>(mn, sh.red);
@@ -859,22 +865,34 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
             const uint32_t j = cb + lane, k = rb + j;
             uint32_t lo = 0, hi = 0, skip = INF;
             if (j < du) {
-                const uint32_t ev = a.offB[a.adjA[k] + 1];
-                uint32_t p = ws.pos[k], s = ws.seg[k];
-                if (p < ev && (a.seg_win[s] >> LOGW) == kw) {
+                // the cursor in one round of independent loads
+                const uint32_t ev = ws.lim[k];
+                uint32_t p = ws.pos[k], s = ws.seg[k], sw = ws.sw[k];
+                if (p < ev && (sw >> LOGW) == kw) {
                     lo = p;
-                    uint32_t e = a.seg_start[s + 1];
+                    uint32_t e = ws.se[k], nsw = INF, nse = 0;
                     s++;
-                    while (e < ev && (a.seg_win[s] >> LOGW) == kw) {
-                        e = a.seg_start[s + 1];
+                    if (e < ev) {
+                        nsw = a.seg_win[s];
+                        nse = a.seg_start[s + 1];
+                    }
+                    while (e < ev && (nsw >> LOGW) == kw) {
+                        e = nse;
                         s++;
+                        if (e < ev) {
+                            nsw = a.seg_win[s];
+                            nse = a.seg_start[s + 1];
+                        }
                     }
                     hi = e < ev ? e : ev;
                     p = hi;
+                    sw = p < ev ? nsw : INF;
                     ws.pos[k] = p;
                     ws.seg[k] = s;
+                    ws.sw[k] = sw;
+                    ws.se[k] = nse;
                 }
-                if (p < ev) next = min(next, a.seg_win[s] >> LOGW);
+                if (p < ev) next = min(next, sw >> LOGW);
                 if (LOCAL) {
                     skip = a.xA[k];
                     ws.lo[k] = lo;
@@ -994,7 +1012,7 @@ __global__ void k_local_finish(const unsigned long long *twiceB, const uint32_t 
 // ------------------------------------------------------------------ host side
 struct ExactWs {
     uint32_t *seg1, *seg_start, *seg_win, *scan_tmp, *items, *items_wide;
-    uint32_t *wpos, *wseg;
+    uint32_t *wpos, *wseg, *wlim, *wsw, *wse;
     uint8_t *bucket;
     QueueState *q;
 };
@@ -1009,6 +1027,9 @@ static ExactWs carve_exact(Carver &c, const Plan &p) {
     w.items_wide = c.take<uint32_t>(pad64(p.nA));
     w.wpos = c.take<uint32_t>(pad64(p.m));
     w.wseg = c.take<uint32_t>(pad64(p.m));
+    w.wlim = c.take<uint32_t>(pad64(p.m));
+    w.wsw = c.take<uint32_t>(pad64(p.m));
+    w.wse = c.take<uint32_t>(pad64(p.m));
     w.bucket = c.take<uint8_t>(pad64(p.nA));
     w.q = c.take<QueueState>(1);
     return w;
@@ -1171,7 +1192,7 @@ int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt
     a.cntE = ce;
     a.twiceB = w.twiceB;
     a.pass2 = (ce != nullptr || cntB != nullptr);
-    WideScratch ws = {w.e.wpos, w.e.wseg, w.wlo, w.whi, w.esum};
+    WideScratch ws = {w.e.wpos, w.e.wseg, w.e.wlim, w.e.wsw, w.e.wse, w.wlo, w.whi, w.esum};
     unsigned gn, gw;
     BFC_TRY(grids(gn, gw));
     k_local_narrow<<<gn, WT, 0, s>>>(a);
@@ -1201,7 +1222,7 @@ static int launch_count(const Plan &p, const ExactWs &w, const bfc_tuning *t,
     BFC_TRY(grids(gn, gw, &r));
     k_exact_narrow<<<gn, WT, 0, s>>>(a);
     a.total = total;
-    WideScratch ws = {w.wpos, w.wseg, nullptr, nullptr, nullptr};
+    WideScratch ws = {w.wpos, w.wseg, w.wlim, w.wsw, w.wse, nullptr, nullptr, nullptr};
     k_exact_wide<<<gw, NT, 0, s>>>(a, ws);
     BFC_HIP(hipGetLastError());
     return BFC_OK;

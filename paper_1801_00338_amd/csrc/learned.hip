@@ -387,21 +387,27 @@ __global__ __launch_bounds__(MLP_WAVES * WAVE) void k_mlp_grad(MlpArgs a) {
 }
 
 // grad[j] (and *loss for j = P_N) = sum over the waves of the partial rows,
-// in wave order: four waves of a block each sum a quarter of the rows, then
-// the quarters are added in order.
-__global__ __launch_bounds__(256) void k_grad_reduce(const float *part, uint32_t nw, float *grad,
-                                                     float *loss) {
-    __shared__ float q[4][64];
+// in a fixed order: the 16 waves of a block each sum a contiguous sixteenth
+// of the rows for 64 columns, then the sixteen partial sums are added in
+// wave order.
+constexpr int RED_WAVES = 16;
+
+__global__ __launch_bounds__(RED_WAVES * WAVE) void k_grad_reduce(const float *part, uint32_t nw,
+                                                                  float *grad, float *loss) {
+    __shared__ float q[RED_WAVES][WAVE];
     const uint32_t lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const uint32_t j = blockIdx.x * WAVE + lane;
-    const uint32_t per = (nw + 3) / 4, w0 = wv * per, w1 = min(nw, w0 + per);
+    const uint32_t per = (nw + RED_WAVES - 1) / RED_WAVES, w0 = wv * per,
+                   w1 = min(nw, w0 + per);
     float s = 0.f;
     if (j <= (uint32_t)P_N)
         for (uint32_t w = w0; w < w1; w++) s += part[(uint64_t)w * GSTRIDE + j];
     q[wv][lane] = s;
     __syncthreads();
     if (wv == 0 && j <= (uint32_t)P_N) {
-        const float t = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
+        float t = q[0][lane];
+#pragma unroll
+        for (int i = 1; i < RED_WAVES; i++) t += q[i][lane];
         if (j < (uint32_t)P_N) grad[j] = t; else *loss = t;
     }
 }
@@ -565,7 +571,8 @@ int bfc_mlp_grad(const uint16_t *d_x, const float *d_target, const uint32_t *d_i
     a.X = d_x; a.idx = d_idx; a.target = d_target; a.rows = rows; a.prm = d_params;
     a.wbf = d_wbf16; a.part = (float *)d_ws; a.inv_rows = 1.f / (float)rows;
     k_mlp_grad<<<blocks, MLP_WAVES * WAVE, 0, s>>>(a);
-    k_grad_reduce<<<(P_N + 1 + WAVE - 1) / WAVE, 256, 0, s>>>(a.part, nw, d_grad, d_loss);
+    k_grad_reduce<<<(P_N + 1 + WAVE - 1) / WAVE, RED_WAVES * WAVE, 0, s>>>(a.part, nw, d_grad,
+                                                                         d_loss);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }

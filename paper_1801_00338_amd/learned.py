@@ -115,23 +115,32 @@ class Mlp:
               "adam")
 
     # -------------------------------------------------------------- training
+    @staticmethod
+    def batch_orders(n: int, steps: int, batch: int, seed: int, device="cuda"):
+        """The seeded per-epoch row orders that ``train`` walks, on the device."""
+        batch = min(batch, n)
+        per_epoch = max(1, n // batch)
+        epochs = (steps + per_epoch - 1) // per_epoch
+        return [torch.from_numpy(gen.batch_order(seed, n, e).view(np.int32)).to(device)
+                for e in range(epochs)]
+
     def train(self, x: torch.Tensor, target: torch.Tensor, steps: int, batch: int = 65536,
-              lr: float = 1e-3, seed: int = 0, log_every: int = 0):
+              lr: float = 1e-3, seed: int = 0, log_every: int = 0, orders=None):
         """Adam on mini-batches drawn without replacement per epoch (seeded order).
 
+        ``orders`` (from ``batch_orders``) may be prepared beforehand.
         Returns the mean squared errors read back every ``log_every`` steps
         (none if 0); reading them synchronises the stream.
         """
         n = x.shape[0]
         batch = min(batch, n)
         per_epoch = max(1, n // batch)
+        if orders is None:
+            orders = self.batch_orders(n, steps, batch, seed, self.device)
         losses = []
-        order = None
         for s in range(steps):
             e, b = divmod(s, per_epoch)
-            if b == 0:
-                order = torch.from_numpy(gen.batch_order(seed, n, e).view(np.int32)).to(self.device)
-            idx = order[b * batch:(b + 1) * batch]
+            idx = orders[e][b * batch:(b + 1) * batch]
             self.grad(x, target, idx)
             self.adam(lr)
             if log_every and (s + 1) % log_every == 0:
