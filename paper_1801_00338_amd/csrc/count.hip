@@ -728,7 +728,8 @@ template <int TW>
 struct SharedT {
     uint32_t tbl[TW + NT];              // counters, then one zero word per thread
     uint32_t pre[NWAVES][WT], lo[NWAVES][WT], hi[NWAVES][WT], skip[NWAVES][WT];
-    unsigned long long esum[NWAVES][WT];
+    uint32_t esum[NWAVES][WT];          // one window's sums of final counts (< 2^14 * 2^16)
+    uint32_t own[NWAVES][WT];           // 1 + chunk midpoint at its first piece of a round
     uint32_t red[NWAVES + 1];
     unsigned long long red64[NWAVES];
     uint32_t item;
@@ -740,26 +741,6 @@ __device__ inline void clear_table(SharedT<TW> &sh) {
     for (int i = threadIdx.x; i < TW / 4; i += NT) ((uint4 *)sh.tbl)[i] = z;
 }
 
-
-// Piece pi of this wave's chunk (prefix over the chunk's 64 midpoints).
-template <int TW>
-__device__ inline Piece cpiece(const SharedT<TW> &sh, uint32_t wv, uint32_t pi, bool valid) {
-    uint32_t j = 0;
-#pragma unroll
-    for (uint32_t s = WT / 2; s; s >>= 1) j = sh.pre[wv][j + s - 1] <= pi ? j + s : j;
-    j = sh.pre[wv][WT - 1] <= pi ? WT : j;
-    j -= 1;
-    Piece pc;
-    const uint32_t lo = sh.lo[wv][j], hi = sh.hi[wv][j];
-    const uint32_t g0 = (lo >> 2) + (pi - sh.pre[wv][j]) * WK;
-    const uint32_t end = min(hi, (g0 + WK) << 2);
-    pc.base = valid ? g0 << 2 : 0;
-    pc.lo = lo;
-    pc.len = valid ? end - lo : 0;
-    pc.skip = sh.skip[wv][j];
-    pc.j = j;
-    return pc;
-}
 
 // pass 0: add one to the counters of the piece's entries, return the sum of
 // previous values; pass 1: return the sum of the final counters.  HALF: two
@@ -795,7 +776,12 @@ __device__ inline uint32_t cpiece_walk(SharedT<TW> &sh, int pass, const Piece &p
     return s;
 }
 
-// One chunk of 64 midpoints (this wave): publish the sub-runs, walk pieces.
+// One chunk of 64 midpoints (this wave): publish the sub-runs, walk pieces
+// in rounds of 64.  A round's pieces are mapped to midpoints through the
+// wave's owner table (midpoints whose first piece falls in the round, plus
+// the one carried over), and the next round's pieces are loaded while this
+// round's counters are updated (unrolled twice so the buffers swap without
+// copies).
 template <int TW, int HALF>
 __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass, uint32_t lo,
                                   uint32_t hi, uint32_t skip, uint32_t wb,
@@ -804,22 +790,59 @@ __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass,
     const uint32_t np = hi > lo ? (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK : 0;
     const uint32_t inc = wave_incl_scan(np);
     const uint32_t NP = wave_last(inc);
-    sh.pre[wv][lane] = inc - np;
+    const uint32_t first = inc - np;
+    sh.pre[wv][lane] = first;
     sh.lo[wv][lane] = lo;
     sh.hi[wv][lane] = hi;
     sh.skip[wv][lane] = skip;
     if (pass == 1) sh.esum[wv][lane] = 0;
-    wave_sync();
+    if (NP == 0) {
+        esum_mid = 0;
+        wave_sync();
+        return;
+    }
     const uint32_t rounds = (NP + WT - 1) / WT;
+    uint32_t carry = 0;
+    auto map_round = [&](uint32_t r) -> Piece {
+        const uint32_t r0 = r * WT;
+        sh.own[wv][lane] = 0;
+        wave_sync();
+        if (np && first - r0 < (uint32_t)WT) sh.own[wv][first - r0] = lane + 1;
+        wave_sync();
+        const uint32_t o = max(wave_incl_max(sh.own[wv][lane]), carry);
+        carry = wave_last(o);
+        const uint32_t j = min((o ? o : 1u) - 1, (uint32_t)(WT - 1));
+        const uint32_t pi = r0 + lane;
+        const bool valid = pi < NP;
+        Piece pc;
+        const uint32_t plo = sh.lo[wv][j], phi = sh.hi[wv][j];
+        const uint32_t g0 = (plo >> 2) + (pi - sh.pre[wv][j]) * WK;
+        const uint32_t end = min(phi, (g0 + WK) << 2);
+        pc.base = valid ? g0 << 2 : 0;
+        pc.lo = plo;
+        pc.len = valid ? end - plo : 0;
+        pc.skip = sh.skip[wv][j];
+        pc.j = j;
+        return pc;
+    };
     uint32_t part = 0;
-    for (uint32_t r = 0; r < rounds; r++) {
-        const uint32_t pi = lane + r * WT;
-        const Piece pc = cpiece(sh, wv, pi < NP ? pi : 0, pi < NP);
-        uint4 q[WK];
-        wfetch<WK>(a.adjB, pc, q);
+    auto work = [&](const Piece &pc, const uint4 *q) {
         const uint32_t s = cpiece_walk<TW, HALF>(sh, pass, pc, q, wb);
         if (pass == 0) part += s;
-        else if (s) atomicAdd(&sh.esum[wv][pc.j], (unsigned long long)s);
+        else if (s) atomicAdd(&sh.esum[wv][pc.j], s);
+    };
+    Piece p0 = map_round(0);
+    uint4 q0[WK], q1[WK];
+    wfetch<WK>(a.adjB, p0, q0);
+    for (uint32_t r = 0;; r += 2) {
+        Piece p1 = map_round(r + 1);
+        wfetch<WK>(a.adjB, p1, q1);
+        work(p0, q0);
+        if (r + 1 >= rounds) break;
+        p0 = map_round(r + 2);
+        wfetch<WK>(a.adjB, p0, q0);
+        work(p1, q1);
+        if (r + 2 >= rounds) break;
     }
     sum += part;
     wave_sync();
