@@ -383,6 +383,11 @@ __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint
             old[4 * k + i] = atomicAdd(&sh.tbl[b >> 2], (uint32_t)(b != zb) << s8);
         }
     }
+    // Keep the extraction below the sixteen atomics so that they are all in
+    // flight before the first result is waited for: an empty volatile asm
+    // that takes each result (no instruction is emitted).
+#pragma unroll
+    for (int k = 0; k < 4 * WK; k++) asm volatile("" : "+v"(old[k]));
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < 4 * WK; k++) s += (old[k] >> sft[k]) & 0xFFu;
