@@ -775,6 +775,9 @@ __device__ inline uint32_t cpiece_walk(SharedT<TW> &sh, int pass, const Piece &p
             }
         }
     }
+    // all sixteen LDS operations in flight before the first result is used
+#pragma unroll
+    for (int k = 0; k < 4 * WK; k++) asm volatile("" : "+v"(v[k]));
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < 4 * WK; k++) s += v[k];
