@@ -435,6 +435,10 @@ __device__ inline void wclear_all(WShared<LOCAL> &sh) {
 // Walk of one narrow start by one wave.  Lane l owns midpoints l + 64 s.
 // EXACT: endpoints ranked above u.  LOCAL: all endpoints other than u, with
 // the per-midpoint sums of final counts accumulated in sh.esum.
+// In a workgroup of one wave the LDS operations execute in issue order, so
+// ordering them needs only a compiler barrier (no wait for completion).
+__device__ inline void wave_order() { __builtin_amdgcn_wave_barrier(); }
+
 // Order this wave's LDS writes before its later reads (no other wave involved).
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -520,7 +524,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
         }
         if (run <= (uint32_t)WT) {
             sh.own[lane] = 0;
-            __syncthreads();
+            wave_order();
 #pragma unroll
             for (int s = 0; s < WSLOTS; s++)
                 if (cnt[s]) sh.own[first[s]] = lane + s * WT + 1;
@@ -532,13 +536,13 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
     auto finish = [&](const Piece &pc, const uint4 *q, uint32_t wb) -> uint32_t {
         const uint32_t part = wbump(sh, pc, q, wb);
         if (LOCAL && pass2) {
-            __syncthreads();
+            wave_order();
             const uint32_t v = wread(sh, pc, q, wb);
             if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
         }
-        __syncthreads();
+        wave_order();
         wclear(sh, pc, q, wb);
-        __syncthreads();
+        wave_order();
         return part;
     };
 
@@ -551,7 +555,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
     unsigned long long sum = 0;
     uint32_t kw;                        // the published window
     uint32_t NP = next_window(kw);
-    __syncthreads();
+    wave_order();
     Piece pa, pb;
     uint4 qa[WK], qb[WK];
     while (kw != INF) {
@@ -566,12 +570,12 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             auto map_round = [&](uint32_t r, uint32_t &carry) -> Piece {
                 const uint32_t r0 = r * WT;
                 sh.own[lane] = 0;
-                wave_sync();
+                wave_order();
 #pragma unroll
                 for (int s = 0; s < WSLOTS; s++)
                     if (cnt[s] && first[s] - r0 < (uint32_t)WT)
                         sh.own[first[s] - r0] = lane + s * WT + 1;
-                wave_sync();
+                wave_order();
                 const uint32_t o = max(wave_incl_max(sh.own[lane]), carry);
                 carry = wave_last(o);
                 const uint32_t j = min((o ? o : 1u) - 1, (uint32_t)(WSLOTS * WT - 1));
@@ -615,21 +619,21 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
                     if (r + 2 >= rounds) break;
                 }
                 sum += part;
-                __syncthreads();            // every count of the window is final
+                wave_order();            // every count of the window is final
             }
             wclear_all(sh);
-            __syncthreads();
+            wave_order();
             NP = next_window(kw);
-            __syncthreads();
+            wave_order();
             continue;
         }
         // prologue: window kw into (pa, qa), publish the following one
         pa = wpiece_direct(sh, lane, lane < NP);
         wfetch<WK>(a.adjB, pa, qa);
         uint32_t kwa = kw;
-        __syncthreads();
+        wave_order();
         NP = next_window(kw);
-        __syncthreads();
+        wave_order();
         for (;;) {
             // (pa, qa) hold window kwa; window kw is published
             // the next window's loads are issued unconditionally (a lane
@@ -642,7 +646,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             if (!more) break;
             const uint32_t kwb = kw;
             NP = next_window(kw);
-            __syncthreads();
+            wave_order();
             // (pb, qb) hold window kwb; window kw is published
             more = kw != INF && NP <= (uint32_t)WT;
             pa = wpiece_direct(sh, lane, more && lane < NP);
@@ -651,7 +655,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             if (!more) break;
             kwa = kw;
             NP = next_window(kw);
-            __syncthreads();
+            wave_order();
         }
         // here window kw (if any) has more pieces than lanes, or none is left
     }
