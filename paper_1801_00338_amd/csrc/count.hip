@@ -666,7 +666,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
 __device__ inline uint32_t wave_take(QueueState *q, int cls, uint32_t chunk) {
     uint32_t b = 0;
     if (threadIdx.x == 0) b = atomicAdd(&q->head[cls], chunk);
-    return __shfl(b, 0, WT);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
 }
 
 __global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
