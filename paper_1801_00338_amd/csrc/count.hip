@@ -368,9 +368,14 @@ __device__ inline uint32_t wslot(const Piece &pc, uint32_t i, uint32_t w, uint32
 
 // Add one to every counter of the piece; the counters' previous values are
 // what the pairs gain.  A zero word gets a zero increment and returns zero.
-template <bool LOCAL>
+// NIB: 4-bit counters (starts of degree <= 15, so C_u[w] <= 15 and an
+// increment never carries into the next counter), eight per word; entry
+// slots are then nibble indices and the zero word is nibbles 8 z .. 8 z + 7.
+template <bool LOCAL, bool NIB = false>
 __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
-    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * 4;
+    constexpr uint32_t PER = NIB ? 8 : 4, LOGP = NIB ? 3 : 2, BITS = NIB ? 4 : 8;
+    constexpr uint32_t MASK = (1u << BITS) - 1;
+    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * PER;
     uint32_t old[4 * WK], sft[4 * WK];
 #pragma unroll
     for (int k = 0; k < WK; k++) {
@@ -378,9 +383,9 @@ __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const uint32_t b = wslot(pc, 4 * k + i, w[i], wb, zb);
-            const uint32_t s8 = (b & 3u) << 3;
-            sft[4 * k + i] = s8;
-            old[4 * k + i] = atomicAdd(&sh.tbl[b >> 2], (uint32_t)(b != zb) << s8);
+            const uint32_t sb = (b & (PER - 1)) * BITS;
+            sft[4 * k + i] = sb;
+            old[4 * k + i] = atomicAdd(&sh.tbl[b >> LOGP], (uint32_t)(b != zb) << sb);
         }
     }
     // Keep the extraction below the sixteen atomics so that they are all in
@@ -390,22 +395,25 @@ __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint
     for (int k = 0; k < 4 * WK; k++) asm volatile("" : "+v"(old[k]));
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < 4 * WK; k++) s += (old[k] >> sft[k]) & 0xFFu;
+    for (int k = 0; k < 4 * WK; k++) s += (old[k] >> sft[k]) & MASK;
     return s;
 }
 
 // Sum of the counters of the piece's entries.
-template <bool LOCAL>
+template <bool LOCAL, bool NIB = false>
 __device__ inline uint32_t wread(const WShared<LOCAL> &sh, const Piece &pc, const uint4 *q,
                                  uint32_t wb) {
     const uint8_t *t8 = (const uint8_t *)sh.tbl;
-    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * 4;
+    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * (NIB ? 8 : 4);
     uint32_t v[4 * WK];
 #pragma unroll
     for (int k = 0; k < WK; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
-        for (int i = 0; i < 4; i++) v[4 * k + i] = t8[wslot(pc, 4 * k + i, w[i], wb, zb)];
+        for (int i = 0; i < 4; i++) {
+            const uint32_t b = wslot(pc, 4 * k + i, w[i], wb, zb);
+            v[4 * k + i] = NIB ? (sh.tbl[b >> 3] >> ((b & 7u) * 4)) & 0xFu : t8[b];
+        }
     }
     uint32_t s = 0;
 #pragma unroll
@@ -413,15 +421,21 @@ __device__ inline uint32_t wread(const WShared<LOCAL> &sh, const Piece &pc, cons
     return s;
 }
 
-template <bool LOCAL>
+// Clear the piece's counters (nibbles: an atomic and, since other lanes may
+// clear the word's other nibbles at the same time).
+template <bool LOCAL, bool NIB = false>
 __device__ inline void wclear(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
     uint8_t *t8 = (uint8_t *)sh.tbl;
-    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * 4;
+    const uint32_t zb = (WTBL_WORDS + threadIdx.x) * (NIB ? 8 : 4);
 #pragma unroll
     for (int k = 0; k < WK; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
-        for (int i = 0; i < 4; i++) t8[wslot(pc, 4 * k + i, w[i], wb, zb)] = 0;
+        for (int i = 0; i < 4; i++) {
+            const uint32_t b = wslot(pc, 4 * k + i, w[i], wb, zb);
+            if (NIB) atomicAnd(&sh.tbl[b >> 3], ~(0xFu << ((b & 7u) * 4)));
+            else t8[b] = 0;
+        }
     }
 }
 
@@ -445,16 +459,22 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-template <bool LOCAL>
+// NIB: the 4-bit table covers 2^15 ranks (two segment windows); a slot's
+// sub-run of a table window is then one segment or two consecutive ones, so
+// the slot looks two segments ahead (w2/s2, w3/s3).  Windows are indexed in
+// table units (segment window >> LOGW).
+template <bool LOCAL, bool NIB>
 __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, uint32_t rb,
                                         uint32_t du, bool pass2) {
+    constexpr int LOGW = NIB ? 1 : 0;
     const uint32_t lane = threadIdx.x;
     const uint32_t ns = (du + WT - 1) / WT;
     uint32_t p[WSLOTS], ev[WSLOTS], cur[WSLOTS], win[WSLOTS], sn[WSLOTS], w2[WSLOTS], s2[WSLOTS];
+    uint32_t w3[WSLOTS], s3[WSLOTS];
 #pragma unroll
     for (int s = 0; s < WSLOTS; s++) {
-        p[s] = ev[s] = cur[s] = sn[s] = s2[s] = 0;
-        win[s] = w2[s] = INF;
+        p[s] = ev[s] = cur[s] = sn[s] = s2[s] = s3[s] = 0;
+        win[s] = w2[s] = w3[s] = INF;
         uint32_t skip = INF;
         const uint32_t j = lane + s * WT;
         if (s < (int)ns && j < du) {
@@ -467,11 +487,15 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             if (LOCAL) skip = x;
             if (LOCAL ? (ev[s] - pb > 1) : (p[s] < ev[s])) {
                 cur[s] = a.seg1[p[s]] - 1;
-                win[s] = a.seg_win[cur[s]];
+                win[s] = a.seg_win[cur[s]] >> LOGW;
                 sn[s] = a.seg_start[cur[s] + 1];
                 if (sn[s] < ev[s]) {
-                    w2[s] = a.seg_win[cur[s] + 1];
+                    w2[s] = a.seg_win[cur[s] + 1] >> LOGW;
                     s2[s] = a.seg_start[cur[s] + 2];
+                    if (NIB && s2[s] < ev[s]) {
+                        w3[s] = a.seg_win[cur[s] + 2] >> LOGW;
+                        s3[s] = a.seg_start[cur[s] + 3];
+                    }
                 }
             }
         }
@@ -500,19 +524,26 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             // branch-free: the look-ahead loads below must not be merged at
             // a branch join (that would wait for them here)
             const bool act = win[s] == kw;
-            const uint32_t h = sn[s] < ev[s] ? sn[s] : ev[s];
+            const uint32_t h1 = sn[s] < ev[s] ? sn[s] : ev[s];
+            // NIB: the next segment (inside the list) in the same table window
+            const bool two = NIB && act && h1 < ev[s] && w2[s] == kw;
+            const uint32_t h = two ? (s2[s] < ev[s] ? s2[s] : ev[s]) : h1;
             const uint32_t lo = act ? p[s] : 0u, hi = act ? h : 0u;
             const uint32_t np = act ? (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK : 0u;
             const bool adv = act && h < ev[s];
             p[s] = act ? h : p[s];
-            cur[s] += adv ? 1u : 0u;
-            win[s] = act ? (adv ? w2[s] : INF) : win[s];
-            sn[s] = adv ? s2[s] : sn[s];
+            cur[s] += adv ? (two ? 2u : 1u) : 0u;
+            win[s] = act ? (adv ? (two ? w3[s] : w2[s]) : INF) : win[s];
+            sn[s] = adv ? (two ? s3[s] : s2[s]) : sn[s];
             // look-ahead from the cursor (unchanged values when it did not
-            // move); used from the next window on.  cur + 2 <= segments + 1,
+            // move); used from the next window on.  cur + 3 <= segments + 2,
             // inside the padded segment arrays.
-            w2[s] = a.seg_win[cur[s] + 1];
+            w2[s] = a.seg_win[cur[s] + 1] >> LOGW;
             s2[s] = a.seg_start[cur[s] + 2];
+            if (NIB) {
+                w3[s] = a.seg_win[cur[s] + 2] >> LOGW;
+                s3[s] = a.seg_start[cur[s] + 3];
+            }
             const uint32_t inc = wave_incl_scan(np);
             const uint32_t j = lane + s * WT;
             sh.pre[j] = run + inc - np;
@@ -534,14 +565,14 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
 
     // Bump, second look and clear of one window held in registers.
     auto finish = [&](const Piece &pc, const uint4 *q, uint32_t wb) -> uint32_t {
-        const uint32_t part = wbump(sh, pc, q, wb);
+        const uint32_t part = wbump<LOCAL, NIB>(sh, pc, q, wb);
         if (LOCAL && pass2) {
             wave_order();
-            const uint32_t v = wread(sh, pc, q, wb);
+            const uint32_t v = wread<LOCAL, NIB>(sh, pc, q, wb);
             if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
         }
         wave_order();
-        wclear(sh, pc, q, wb);
+        wclear<LOCAL, NIB>(sh, pc, q, wb);
         wave_order();
         return part;
     };
@@ -565,7 +596,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             // in the round, plus the one carried over from the round
             // before), and the next round's pieces are loaded while this
             // round's counters are bumped (unrolled twice, no copies).
-            const uint32_t wb = kw << G_SHIFT;
+            const uint32_t wb = kw << (G_SHIFT + LOGW);
             const uint32_t rounds = (NP + WT - 1) / WT;
             auto map_round = [&](uint32_t r, uint32_t &carry) -> Piece {
                 const uint32_t r0 = r * WT;
@@ -602,18 +633,18 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
                     Piece r1p = map_round(r + 1, carry);
                     wfetch<WK>(a.adjB, r1p, q1);
                     if (pass == 0) {
-                        part += wbump(sh, r0p, q0, wb);
+                        part += wbump<LOCAL, NIB>(sh, r0p, q0, wb);
                     } else {
-                        const uint32_t v = wread(sh, r0p, q0, wb);
+                        const uint32_t v = wread<LOCAL, NIB>(sh, r0p, q0, wb);
                         if (v) atomicAdd(&sh.esum[r0p.j], (unsigned long long)v);
                     }
                     if (r + 1 >= rounds) break;
                     r0p = map_round(r + 2, carry);
                     wfetch<WK>(a.adjB, r0p, q0);
                     if (pass == 0) {
-                        part += wbump(sh, r1p, q1, wb);
+                        part += wbump<LOCAL, NIB>(sh, r1p, q1, wb);
                     } else {
-                        const uint32_t v = wread(sh, r1p, q1, wb);
+                        const uint32_t v = wread<LOCAL, NIB>(sh, r1p, q1, wb);
                         if (v) atomicAdd(&sh.esum[r1p.j], (unsigned long long)v);
                     }
                     if (r + 2 >= rounds) break;
@@ -642,7 +673,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             bool more = kw != INF && NP <= (uint32_t)WT;
             pb = wpiece_direct(sh, lane, more && lane < NP);
             wfetch<WK>(a.adjB, pb, qb);
-            sum += finish(pa, qa, kwa << G_SHIFT);
+            sum += finish(pa, qa, kwa << (G_SHIFT + LOGW));
             if (!more) break;
             const uint32_t kwb = kw;
             NP = next_window(kw);
@@ -651,7 +682,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             more = kw != INF && NP <= (uint32_t)WT;
             pa = wpiece_direct(sh, lane, more && lane < NP);
             wfetch<WK>(a.adjB, pa, qa);
-            sum += finish(pb, qb, kwb << G_SHIFT);
+            sum += finish(pb, qb, kwb << (G_SHIFT + LOGW));
             if (!more) break;
             kwa = kw;
             NP = next_window(kw);
@@ -681,7 +712,9 @@ __global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
         for (uint32_t it = b; it < e; it++) {
             const uint32_t u = a.items[it];
             const uint32_t rb = a.offA[u];
-            const unsigned long long s = wave_walk<false>(a, sh, rb, a.offA[u + 1] - rb, false);
+            const uint32_t du = a.offA[u + 1] - rb;
+            const unsigned long long s = du <= 15u ? wave_walk<false, true>(a, sh, rb, du, false)
+                                                   : wave_walk<false, false>(a, sh, rb, du, false);
             if (a.per_start) {
                 const unsigned long long t = wave_sum64(s);
                 if (threadIdx.x == 0) a.per_start[u] = t;
@@ -704,7 +737,8 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
         for (uint32_t it = b; it < e; it++) {
             const uint32_t u = a.c.items[it];
             const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
-            unsigned long long s = wave_walk<true>(a.c, sh, rb, du, a.pass2);
+            unsigned long long s = du <= 15u ? wave_walk<true, true>(a.c, sh, rb, du, a.pass2)
+                                             : wave_walk<true, false>(a.c, sh, rb, du, a.pass2);
             if (a.pass2) {
                 for (uint32_t j = threadIdx.x; j < du; j += WT) {
                     const uint32_t k = rb + j;
@@ -1055,8 +1089,8 @@ struct ExactWs {
 static ExactWs carve_exact(Carver &c, const Plan &p) {
     ExactWs w;
     w.seg1 = c.take<uint32_t>(pad64(p.m));
-    w.seg_start = c.take<uint32_t>(pad64(p.m + 1));
-    w.seg_win = c.take<uint32_t>(pad64(p.m));
+    w.seg_start = c.take<uint32_t>(pad64(p.m + 3));   // look-ahead reads up to segments + 2
+    w.seg_win = c.take<uint32_t>(pad64(p.m + 2));
     w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(p.m));
     w.items = c.take<uint32_t>(pad64(p.nA));
     w.items_wide = c.take<uint32_t>(pad64(p.nA));
