@@ -533,8 +533,15 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             const bool adv = act && h < ev[s];
             p[s] = act ? h : p[s];
             cur[s] += adv ? (two ? 2u : 1u) : 0u;
-            win[s] = act ? (adv ? (two ? w3[s] : w2[s]) : INF) : win[s];
-            sn[s] = adv ? (two ? s3[s] : s2[s]) : sn[s];
+            // bitwise blends rather than selects between the look-ahead
+            // registers (a select of two array elements can be turned into a
+            // load through a selected address, which keeps the arrays in
+            // scratch memory)
+            const uint32_t tm = 0u - (uint32_t)two;
+            const uint32_t nw = w2[s] ^ ((w2[s] ^ w3[s]) & tm);
+            const uint32_t ne = s2[s] ^ ((s2[s] ^ s3[s]) & tm);
+            win[s] = act ? (adv ? nw : INF) : win[s];
+            sn[s] = adv ? ne : sn[s];
             // look-ahead from the cursor (unchanged values when it did not
             // move); used from the next window on.  cur + 3 <= segments + 2,
             // inside the padded segment arrays.
