@@ -144,6 +144,9 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
             t += offB[v + 1] - (all_ends ? offB[v] : xA[k]) - 1;
         }
         t = wave_sum64(t);
+        // a start with one midpoint shares at most one with any w: C_u[w] <= 1
+        // adds nothing to a count, so it is not queued (its outputs stay 0)
+        if (re - rb < 2) t = 0;
         if (lane == 0) {
             uint32_t b = t ? 64 - __clzll(t) : 0;
             uint32_t cls = (re - rb) > narrow_max;
