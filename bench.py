@@ -254,6 +254,101 @@ def learned_vs_uniform(dev, trials):
     return out
 
 
+def bench_batch(args):
+    """Throughput of the batched exact count: 1,024 uneven graphs in one union."""
+    import numpy as np
+    import torch
+
+    from paper_1801_00338_amd import api, gen
+
+    t0 = time.perf_counter()
+    graphs = gen.batch_graphs(1024, 1_000, 2_000_000, seed=3)
+    m = sum(len(g[2]) for g in graphs)
+    log(f"generated 1024 graphs, m={m} in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    b = api.Batch(graphs, device=dev)
+    torch.cuda.synchronize(dev)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    W = b.wedges
+    best, tuned_ms = b.autotune()
+    log(f"union built in {build_ms:.0f} ms; wedges={W}; autotuned {best.as_dict()} {tuned_ms:.2f} ms")
+    out = torch.zeros(1024, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        b.totals_async(out, best)
+    torch.cuda.synchronize(dev)
+    ref = out.clone()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        b.totals_async(out, best)
+        e1.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    if args.warmup and not torch.equal(out, ref):
+        raise SystemExit("batch totals changed between runs")
+    ms = wall * 1e3 / args.steps
+    line = {
+        "metric": "graphs/s (batched exact counts)", "value": 1024 / (ms * 1e-3),
+        "unit": "graphs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batch_1024 (m log-uniform in [1k, 2M], seed 3)", "graphs": 1024,
+                   "edges": m, "wedges": W, "tuning": best.as_dict(),
+                   "step": "plan + exact count of every graph + per-graph sums, one union"},
+        "wedges_per_s": W / (ms * 1e-3),
+        "gpu_ms_per_step": sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps,
+        "union_build_once_ms": build_ms,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_replicas(args):
+    """The 256-replica ESpar/ClrSpar batch on the 10M/30M/100M-edge graph."""
+    import numpy as np
+    import torch
+
+    from paper_1801_00338_amd import api, gen
+
+    w = gen.WORKLOADS["chung_lu_10m_30m_100m"]
+    l, r = w.edges()
+    dev = torch.device("cuda:0")
+    g = api.Graph(w.nl, w.nr, l, r, device=dev)
+    del l, r
+    B = g.exact()
+    reps = []
+    for p in (0.01, 0.02, 0.05, 0.1):
+        reps += [("espar", p, (4 << 32) | len(reps) + i) for i in range(32)]
+    for n in (4, 8, 16, 32):
+        reps += [("clrspar", n, (4 << 32) | len(reps) + i) for i in range(32)]
+    times = []
+    for it in range(max(1, args.steps)):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        beta, est, kept = g.spar_batch(reps, log=log)
+        times.append(time.perf_counter() - t0)
+    groups = {}
+    for i in range(0, 256, 32):
+        kind, param, _ = reps[i]
+        e = est[i:i + 32]
+        groups[f"{kind}:{param}"] = {"mean": float(e.mean()), "rel_err": float((e.mean() - B) / B),
+                                     "var": float(e.var(ddof=1))}
+    ms = min(times) * 1e3
+    line = {
+        "metric": "replicas/s (batched sparsification estimators)", "value": 256 / (ms * 1e-3),
+        "unit": "replicas/s", "n_gpus": 1, "steps": len(times), "warmup": 0,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": dict(w.describe(), replicas=256, butterflies=B, kept_edges=int(kept.sum()),
+                       step="filters, compaction, union build and one count of all replicas"),
+        "groups": groups,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +384,10 @@ def main():
         log(f"copied {n} bytes three times")
         return
 
+    if args.workload == "batch_1024":
+        return bench_batch(args)
+    if args.workload == "replicas_256":
+        return bench_replicas(args)
     w = gen.WORKLOADS[args.workload]
     t0 = time.perf_counter()
     l, r = w.edges()
