@@ -68,6 +68,8 @@ def lib():
         L.orc_clrspar.argtypes = g + [C.c_uint32, C.c_uint64, u64p, dp, u64p]
         L.orc_vsamp.argtypes = g + [dp, C.c_uint64, C.c_uint64, u32p, u64p, dp]
         L.orc_esamp.argtypes = g + [dp, C.c_uint64, C.c_uint64, u64p, u64p, dp]
+        L.orc_esamp_fast.argtypes = g + [dp, C.c_uint64, C.c_uint32, C.c_uint64, u64p, u32p, dp]
+        L.orc_fast_ebfc_pairs.argtypes = g + [C.c_uint64, u64p]
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_philox4x32_10.restype = None
         L.orc_color.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
@@ -198,6 +200,29 @@ def esamp(nl, nr, l, r, k, seed, probs=None):
     _check(lib().orc_esamp(*_g(nl, nr, l, r), pp, k, seed, _p(eids, C.c_uint64),
                            _p(cnt, C.c_uint64), C.byref(est)))
     return eids, cnt, est.value
+
+
+def esamp_fast(nl, nr, l, r, k, alpha, seed, probs=None):
+    """ESamp with Fast-eBFC (Sec. 5.5): returns (edge indices[k], hits[k], estimate)."""
+    l, r = _edges(l, r)
+    eids = np.zeros(k, np.uint64)
+    hits = np.zeros(k, np.uint32)
+    est = C.c_double()
+    pp = None
+    if probs is not None:
+        probs = np.ascontiguousarray(probs, dtype=np.float64)
+        pp = _p(probs, C.c_double)
+    _check(lib().orc_esamp_fast(*_g(nl, nr, l, r), pp, k, alpha, seed, _p(eids, C.c_uint64),
+                                _p(hits, C.c_uint32), C.byref(est)))
+    return eids, hits, est.value
+
+
+def fast_ebfc_pairs(nl, nr, l, r, e):
+    """Hitting neighbour pairs of input edge e over all d_a * d_x picks."""
+    l, r = _edges(l, r)
+    out = C.c_uint64()
+    _check(lib().orc_fast_ebfc_pairs(*_g(nl, nr, l, r), e, C.byref(out)))
+    return out.value
 
 
 def philox(ctr, key):

@@ -665,6 +665,182 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------------------------ */
+/* ESamp with Fast-eBFC (Sec. 5.5): the drawn edge's count is not       */
+/* counted but estimated.  One trial for edge e = (a, x), a in L, x in R: */
+/* pick b uniformly from the neighbours of x and y uniformly from the    */
+/* neighbours of a; the trial hits iff b != a, y != x and (b, y) is an   */
+/* edge, i.e. {a, b} x {x, y} is a butterfly.  hit * d_a * d_x has mean  */
+/* B_e (the lemma of Sec. 5.5), since exactly B_e of the d_a * d_x pairs */
+/* (b, y) hit.  Picking from the whole neighbourhood (b = a or y = x is  */
+/* simply a miss) keeps that scale exact.                                */
+/*                                                                      */
+/* Draw i picks the edge exactly as ESamp above (same stream, same ids). */
+/* Trial j of draw i (i < 2^32) uses the Philox counter                  */
+/* (i, j, TAG_FAST, attempt): x1 = out0 | out1 << 32, x2 = out2 | out3   */
+/* << 32; the attempt is kept iff x1 < 2^64 - 2^64 mod d_x and x2 <      */
+/* 2^64 - 2^64 mod d_a, then b is neighbour x1 mod d_x of x and y is     */
+/* neighbour x2 mod d_a of a.  Neighbours are listed in ascending order   */
+/* of (degree, id) on their side.                                        */
+/*                                                                      */
+/* hits_i = number of hits among alpha trials.  Estimate: term_i =       */
+/* ((double)hits_i * (double)(d_a * d_x)) * s_i with s_i = (double)m / 4 */
+/* (uniform) or (double)Q / (4.0 * (double)q_i) (weighted), summed left  */
+/* to right in blocks of 1024 draws and the block sums left to right,    */
+/* divided by ((double)k * (double)alpha).                               */
+/* ------------------------------------------------------------------ */
+#define TAG_FAST 0x46454243u    /* neighbour pair of a Fast-eBFC trial */
+
+static const uint64_t *fast_deg_key;    /* degrees of the side being sorted */
+static int deg_id_cmp(const void *pa, const void *pb) {
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    uint64_t da = fast_deg_key[a], db = fast_deg_key[b];
+    if (da != db) return da < db ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
+/* Neighbours of v (row v of A, ids of the other side) in (degree, id)
+ * order of the other side, whose degrees are deg. */
+static void list_by_degree(const adj_t *A, uint32_t v, const uint64_t *deg, uint32_t *out) {
+    uint64_t b = A->off[v], d = A->off[v + 1] - b;
+    for (uint64_t k = 0; k < d; k++) out[k] = A->nbr[b + k];
+    fast_deg_key = deg;
+    qsort(out, d, sizeof(uint32_t), deg_id_cmp);
+}
+
+static int has_edge(const adj_t *L, uint32_t b, uint32_t y) {
+    uint64_t lo = L->off[b], hi = L->off[b + 1];    /* row b sorted by id */
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (L->nbr[mid] == y) return 1;
+        if (L->nbr[mid] < y) lo = mid + 1; else hi = mid;
+    }
+    return 0;
+}
+
+/* The trial's test on picked neighbours b (of x) and y (of a). */
+static int fast_hit(const graph_t *g, uint32_t a, uint32_t x, uint32_t b, uint32_t y) {
+    return b != a && y != x && has_edge(&g->L, b, y);
+}
+
+typedef struct { uint64_t *deg_l, *deg_r; uint32_t *nb_x, *nb_a; } fast_tmp_t;
+
+static void fast_tmp_free(fast_tmp_t *t) {
+    free(t->deg_l); free(t->deg_r); free(t->nb_x); free(t->nb_a);
+}
+
+static int fast_tmp_init(fast_tmp_t *t, const graph_t *g) {
+    uint32_t maxd = 1;
+    t->deg_l = (uint64_t *)malloc(((size_t)g->L.n + 1) * 8);
+    t->deg_r = (uint64_t *)malloc(((size_t)g->R.n + 1) * 8);
+    for (uint32_t v = 0; t->deg_l && v < g->L.n; v++) {
+        t->deg_l[v] = g->L.off[v + 1] - g->L.off[v];
+        if (t->deg_l[v] > maxd) maxd = (uint32_t)t->deg_l[v];
+    }
+    for (uint32_t v = 0; t->deg_r && v < g->R.n; v++) {
+        t->deg_r[v] = g->R.off[v + 1] - g->R.off[v];
+        if (t->deg_r[v] > maxd) maxd = (uint32_t)t->deg_r[v];
+    }
+    t->nb_x = (uint32_t *)malloc((size_t)maxd * 4);
+    t->nb_a = (uint32_t *)malloc((size_t)maxd * 4);
+    if (!t->deg_l || !t->deg_r || !t->nb_x || !t->nb_a) { fast_tmp_free(t); return ORC_E_NOMEM; }
+    return ORC_OK;
+}
+
+/* alpha trials on edge (a, x) for draw i. */
+static uint32_t fast_trials(const graph_t *g, fast_tmp_t *t, uint32_t a, uint32_t x, uint32_t i,
+                            uint32_t alpha, uint64_t seed) {
+    uint64_t da = g->L.off[a + 1] - g->L.off[a];
+    uint64_t dx = g->R.off[x + 1] - g->R.off[x];
+    list_by_degree(&g->R, x, t->deg_l, t->nb_x);    /* neighbours of x: L ids */
+    list_by_degree(&g->L, a, t->deg_r, t->nb_a);    /* neighbours of a: R ids */
+    uint64_t rem_x = (0 - dx) % dx, rem_a = (0 - da) % da;
+    uint32_t key[2], ctr[4], out[4], hits = 0;
+    seed_key(seed, key);
+    for (uint32_t j = 0; j < alpha; j++) {
+        uint64_t x1, x2;
+        for (uint32_t attempt = 0;; attempt++) {
+            ctr[0] = i; ctr[1] = j; ctr[2] = TAG_FAST; ctr[3] = attempt;
+            orc_philox4x32_10(ctr, key, out);
+            x1 = (uint64_t)out[0] | ((uint64_t)out[1] << 32);
+            x2 = (uint64_t)out[2] | ((uint64_t)out[3] << 32);
+            if ((rem_x == 0 || x1 < (uint64_t)(0 - rem_x)) &&
+                (rem_a == 0 || x2 < (uint64_t)(0 - rem_a)))
+                break;
+        }
+        hits += (uint32_t)fast_hit(g, a, x, t->nb_x[x1 % dx], t->nb_a[x2 % da]);
+    }
+    return hits;
+}
+
+int orc_esamp_fast(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l, const uint32_t *r,
+                   const double *probs, uint64_t k, uint32_t alpha, uint64_t seed,
+                   uint64_t *eids, uint32_t *hits, double *est) {
+    if (k == 0 || k > 0xFFFFFFFFull || alpha == 0 || !eids || !hits || !est || m == 0)
+        return ORC_E_ARG;
+    graph_t g;
+    fast_tmp_t t;
+    uint32_t *q = NULL, *qd = NULL;
+    uint64_t *pre = NULL, Q = 0;
+    double total = 0.0, part = 0.0;
+    int rc = graph_build(&g, nl, nr, m, l, r);
+    if (rc) return rc;
+    rc = fast_tmp_init(&t, &g);
+    if (rc) { graph_free(&g); return rc; }
+    if (probs) {
+        q = (uint32_t *)malloc(m * 4); pre = (uint64_t *)malloc(m * 8); qd = (uint32_t *)malloc(k * 4);
+        if (!q || !pre || !qd) { rc = ORC_E_NOMEM; goto done; }
+        rc = quantise(probs, m, q, &Q);
+        if (rc) goto done;
+        uint64_t run = 0;
+        for (uint64_t j = 0; j < m; j++) { run += q[j]; pre[j] = run; }
+    }
+    for (uint64_t i = 0; i < k; i++) {
+        uint64_t e;
+        if (probs) {
+            uint64_t u = uniform_below(seed, (uint32_t)i, (uint32_t)(i >> 32), TAG_EDRAW, Q);
+            e = pick_weighted(pre, m, u);
+            qd[i] = q[e];
+        } else {
+            e = uniform_below(seed, (uint32_t)i, (uint32_t)(i >> 32), TAG_EDRAW, m);
+        }
+        eids[i] = e;
+        uint32_t a = l[e], x = r[e];
+        hits[i] = fast_trials(&g, &t, a, x, (uint32_t)i, alpha, seed);
+        uint64_t dd = (g.L.off[a + 1] - g.L.off[a]) * (g.R.off[x + 1] - g.R.off[x]);
+        double s = probs ? (double)Q / (4.0 * (double)qd[i]) : (double)m / 4.0;
+        part += ((double)hits[i] * (double)dd) * s;
+        if ((i + 1) % COMBINE_BLOCK == 0 || i + 1 == k) { total += part; part = 0.0; }
+    }
+    *est = total / ((double)k * (double)alpha);
+done:
+    free(q); free(pre); free(qd); fast_tmp_free(&t); graph_free(&g);
+    return rc;
+}
+
+/* Number of hitting (b, y) pairs over every pick of the two neighbours of
+ * input edge e: the lemma of Sec. 5.5 says it is B_e. */
+int orc_fast_ebfc_pairs(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l,
+                        const uint32_t *r, uint64_t e, uint64_t *pairs) {
+    if (!pairs || e >= m) return ORC_E_ARG;
+    graph_t g;
+    fast_tmp_t t;
+    int rc = graph_build(&g, nl, nr, m, l, r);
+    if (rc) return rc;
+    rc = fast_tmp_init(&t, &g);
+    if (rc) { graph_free(&g); return rc; }
+    uint32_t a = l[e], x = r[e];
+    uint64_t da = g.L.off[a + 1] - g.L.off[a], dx = g.R.off[x + 1] - g.R.off[x], s = 0;
+    list_by_degree(&g.R, x, t.deg_l, t.nb_x);
+    list_by_degree(&g.L, a, t.deg_r, t.nb_a);
+    for (uint64_t jb = 0; jb < dx; jb++)
+        for (uint64_t jy = 0; jy < da; jy++) s += (uint64_t)fast_hit(&g, a, x, t.nb_x[jb], t.nb_a[jy]);
+    *pairs = s;
+    fast_tmp_free(&t);
+    graph_free(&g);
+    return ORC_OK;
+}
+
 /* Raw draws only (for statistics tests that do not need the counts). */
 int orc_uniform_below(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag, uint64_t n,
                       uint64_t *out) {
