@@ -202,6 +202,27 @@ int bfc_esamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
 int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
               uint64_t *d_eids, uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
               hipStream_t stream);
+/* ESamp with Fast-eBFC (Sec. 5.5): the edges are drawn exactly as bfc_esamp
+ * draws them (same seed: same d_eids), but each drawn edge's count is
+ * estimated, not counted.  Draw i (k < 2^32) runs alpha >= 1 trials on its
+ * edge e = (a, x): trial j picks a neighbour b of x and a neighbour y of a
+ * uniformly (one Philox block at counter (i, j, 'FEBC', attempt), words
+ * 0-1 for b and 2-3 for y, both by rejection; neighbours in ascending rank
+ * order) and hits iff b != a, y != x and (b, y) is an edge.  Exactly B_e of
+ * the d_a * d_x picks hit, so hits * d_a * d_x / alpha is an unbiased
+ * estimate of B_e (the lemma of Sec. 5.5).
+ * d_eids[i] (uint64): the drawn edge's index in the caller's edge list;
+ * d_hits[i] (uint32): its number of hits; *d_est: term_i = ((double)hits_i
+ * * (double)(d_a * d_x)) * s_i with s_i = (double)m / 4 (uniform) or
+ * Q / (4.0 * q_i) (weighted, as bfc_esamp), summed left to right within
+ * blocks of 1024 draws, block sums left to right, divided by
+ * ((double)k * (double)alpha).  BFC_E_ARG for k == 0, k >= 2^32 or
+ * alpha == 0; BFC_E_PROBS as bfc_esamp.  Asynchronous without d_probs; with
+ * d_probs it synchronises once to validate them. */
+int bfc_esamp_fast_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
+int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32_t alpha,
+                   uint64_t seed, uint64_t *d_eids, uint32_t *d_hits, double *d_est,
+                   void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batched exact counts: many graphs counted in one persistent launch.      */

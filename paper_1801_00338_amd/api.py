@@ -232,6 +232,43 @@ class Graph:
         return self._samp(L.bfc_esamp_ws_size, L.bfc_esamp, self.n_edges, k, seed, probs,
                           torch.int64)
 
+    def esamp_fast_buffers(self, k):
+        """Device buffers for esamp_fast_async with k draws."""
+        sz = C.c_size_t()
+        check(lib().bfc_esamp_fast_ws_size(C.byref(self.g), k, C.byref(sz)), "esamp_fast ws size")
+        return dict(ws=_bytes(sz.value, self.device), k=k,
+                    eids=torch.zeros(max(k, 1), dtype=torch.int64, device=self.device),
+                    hits=torch.zeros(max(k, 1), dtype=torch.int32, device=self.device),
+                    est=torch.zeros(1, dtype=torch.float64, device=self.device))
+
+    def esamp_fast_async(self, bufs, alpha, seed, probs=None, stream=None):
+        """ESamp with Fast-eBFC into ``bufs`` (from esamp_fast_buffers); no synchronisation
+        unless ``probs`` (a device float64 tensor of n_edges) is given."""
+        pp = None
+        if probs is not None:
+            if probs.numel() != self.n_edges or probs.dtype != torch.float64:
+                raise ValueError("probs must be n_edges float64 values")
+            pp = C.c_void_p(probs.data_ptr())
+        ws = bufs["ws"]
+        check(lib().bfc_esamp_fast(C.byref(self.g), pp, bufs["k"], alpha, seed,
+                                   C.c_void_p(bufs["eids"].data_ptr()),
+                                   C.c_void_p(bufs["hits"].data_ptr()),
+                                   C.c_void_p(bufs["est"].data_ptr()), C.c_void_p(ws.data_ptr()),
+                                   ws.numel(), _stream(stream)), "esamp_fast")
+
+    def esamp_fast(self, k, alpha, seed, probs=None):
+        """ESamp with Fast-eBFC: (drawn edge indices, hits per draw, estimate)."""
+        bufs = self.esamp_fast_buffers(k)
+        if probs is not None and not isinstance(probs, torch.Tensor):
+            probs = torch.as_tensor(np.ascontiguousarray(probs, dtype=np.float64))
+        if probs is not None:
+            probs = probs.to(device=self.device, dtype=torch.float64).contiguous()
+        self.esamp_fast_async(bufs, alpha, seed, probs)
+        torch.cuda.synchronize(self.device)
+        return (bufs["eids"].cpu().numpy().view(np.uint64)[:k].copy(),
+                bufs["hits"].cpu().numpy().view(np.uint32)[:k].copy(),
+                float(bufs["est"].item()))
+
     # -------------------------------------------------------------- batching
     def exact_tuned(self, tuning=None, side=BFC_SIDE_AUTO):
         """bfc_exact with a launch shape (a bfc_tuning, a dict of its fields, or None)."""

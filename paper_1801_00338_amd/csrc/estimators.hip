@@ -13,6 +13,10 @@
 //   draw i of VSamp / ESamp:     counter (i lo, i hi, 'VDRW' / 'EDRW', attempt),
 //                                x = out0 | out1 << 32, rejected while
 //                                x >= 2^64 - 2^64 mod n, value x mod n
+//   trial j of Fast-eBFC draw i: counter (i, j, 'FEBC', attempt), x1 = out0 | out1 << 32,
+//                                x2 = out2 | out3 << 32, both rejected as above
+//                                (bounds d_x and d_a), neighbour picks x1 mod d_x
+//                                and x2 mod d_a in ascending rank order
 // Weighted draws quantise probabilities to integer weights
 // q_j = prob_j > 0 ? max(1, floor(prob_j / max(prob) * (2^32 - 1))) : 0 and
 // pick the first j whose inclusive prefix sum of q exceeds a uniform draw
@@ -27,6 +31,7 @@ constexpr uint32_t TAG_ESPAR = 0x45535052u;
 constexpr uint32_t TAG_COLOR = 0x434C5253u;
 constexpr uint32_t TAG_VDRAW = 0x56445257u;
 constexpr uint32_t TAG_EDRAW = 0x45445257u;
+constexpr uint32_t TAG_FAST = 0x46454243u;
 constexpr uint32_t COMBINE_BLOCK = 1024;   // draws summed left to right per block
 
 // ------------------------------------------------------------------ Philox
@@ -362,6 +367,116 @@ __global__ __launch_bounds__(256) void k_combine(uint64_t k, uint64_t n,
             *est = ((double)t * (double)n) / (4.0 * (double)k);
             if (ovf) f->overflow = 1;
         }
+    }
+}
+
+// ------------------------------------------------------------------ Fast-eBFC
+// ESamp with Fast-eBFC (Sec. 5.5): each drawn edge e = (a, x) gets alpha
+// trials; a trial picks b among the neighbours of x and y among those of a
+// and hits iff b != a, y != x and (b, y) is an edge.  hits * d_a * d_x has
+// mean B_e.
+struct FastArgs {
+    const uint32_t *off_l, *adj_l, *off_r, *adj_r;
+    const uint32_t *ea, *ex;        // per draw: L rank and R rank of the edge
+    uint64_t k, seed;
+    uint32_t alpha;
+};
+
+// Per draw: the drawn edge's endpoints as ranks (pos = L-side CSR position
+// of every input edge); clears the hit counter and reports the edge index.
+__global__ void k_fast_setup(uint64_t k, const unsigned long long *draw, const uint32_t *pos,
+                             const uint32_t *off_l, uint32_t nl, const uint32_t *adj_l,
+                             uint32_t *ea, uint32_t *ex, uint32_t *hits,
+                             unsigned long long *eids) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < k;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = pos[draw[i]];
+        uint32_t lo = 0, hi = nl;             // row a with off_l[a] <= p < off_l[a+1]
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (off_l[mid + 1] > p) hi = mid; else lo = mid + 1;
+        }
+        ea[i] = lo;
+        ex[i] = adj_l[p];
+        hits[i] = 0;
+        eids[i] = draw[i];
+    }
+}
+
+__device__ inline bool in_sorted(const uint32_t *a, uint32_t n, uint32_t t) {
+    uint32_t lo = 0, hi = n;                  // first position with a[pos] >= t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    return lo < n && a[lo] == t;
+}
+
+// One wave per (draw, 64 consecutive trials); a wave adds its hits to the
+// draw's counter with one atomic.
+__global__ __launch_bounds__(256) void k_fast_trials(FastArgs f, uint32_t *hits) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    const uint64_t nchunk = (f.alpha + WAVE - 1) / WAVE;
+    const uint64_t units = f.k * nchunk;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+    for (uint64_t u = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE; u < units;
+         u += nwaves) {
+        const uint64_t i = u / nchunk;
+        const uint32_t j = (uint32_t)(u - i * nchunk) * WAVE + lane;
+        bool hit = false;
+        if (j < f.alpha) {
+            const uint32_t a = f.ea[i], x = f.ex[i];
+            const uint32_t la = f.off_l[a], da = f.off_l[a + 1] - la;
+            const uint32_t lx = f.off_r[x], dx = f.off_r[x + 1] - lx;
+            const uint64_t rx = (0 - (uint64_t)dx) % dx, ra = (0 - (uint64_t)da) % da;
+            uint32_t o[4];
+            uint64_t x1, x2;
+            for (uint32_t attempt = 0;; attempt++) {
+                philox((uint32_t)i, j, TAG_FAST, attempt, f.seed, o);
+                x1 = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+                x2 = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+                if ((rx == 0 || x1 < 0 - rx) && (ra == 0 || x2 < 0 - ra)) break;
+            }
+            const uint32_t b = f.adj_r[lx + (uint32_t)(x1 % dx)];   // L rank
+            const uint32_t y = f.adj_l[la + (uint32_t)(x2 % da)];   // R rank
+            if (b != a && y != x) {
+                const uint32_t lb = f.off_l[b], db = f.off_l[b + 1] - lb;
+                const uint32_t ly = f.off_r[y], dy = f.off_r[y + 1] - ly;
+                hit = db <= dy ? in_sorted(f.adj_l + lb, db, y) : in_sorted(f.adj_r + ly, dy, b);
+            }
+        }
+        const uint64_t mask = __ballot(hit);
+        if (lane == 0 && mask) atomicAdd(&hits[i], (uint32_t)__popcll(mask));
+    }
+}
+
+// Estimate: term_i = ((double)hits_i * (double)(d_a d_x)) * s_i with s_i =
+// m / 4 (uniform) or Q / (4 q_i) (weighted), summed left to right within
+// blocks of COMBINE_BLOCK draws, block sums left to right, over k * alpha.
+__global__ __launch_bounds__(256) void k_fast_combine(FastArgs f, uint64_t m, const uint32_t *hits,
+                                                      const uint32_t *wdraw,
+                                                      const unsigned long long *pre,
+                                                      double *parts, double *est) {
+    const uint64_t nb = (f.k + COMBINE_BLOCK - 1) / COMBINE_BLOCK;
+    const double su = (double)m / 4.0;
+    const double Q = pre ? (double)pre[m - 1] : 0.0;
+    for (uint64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        double part = 0.0;
+        const uint64_t e = min((uint64_t)(b + 1) * COMBINE_BLOCK, f.k);
+        for (uint64_t i = b * COMBINE_BLOCK; i < e; i++) {
+            const uint32_t a = f.ea[i], x = f.ex[i];
+            const uint64_t dd = (uint64_t)(f.off_l[a + 1] - f.off_l[a]) *
+                                (f.off_r[x + 1] - f.off_r[x]);
+            const double sc = pre ? Q / (4.0 * (double)wdraw[i]) : su;
+            part += ((double)hits[i] * (double)dd) * sc;
+        }
+        parts[b] = part;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double total = 0.0;
+        for (uint64_t b = 0; b < nb; b++) total += parts[b];
+        *est = total / ((double)f.k * (double)f.alpha);
     }
 }
 
@@ -934,6 +1049,23 @@ static int carve_samp(Carver &c, const bfc_graph *g, uint64_t n, uint64_t k, int
     return BFC_OK;
 }
 
+// Fast-eBFC sampler: the draw buffers of carve_samp, the edge position map
+// and the per-draw endpoints.
+static void carve_fast(Carver &c, uint64_t m, uint64_t k, SampWs &w, uint32_t *&ea,
+                       uint32_t *&ex) {
+    w = SampWs{};
+    w.flags = c.take<ProbFlags>(1);
+    w.w = c.take<unsigned long long>(pad64(m));
+    w.pre = c.take<unsigned long long>(pad64(m));
+    w.scan_tmp = c.take<unsigned long long>((m + S64_TILE - 1) / S64_TILE + 64);
+    w.draw = c.take<unsigned long long>(pad64(k));
+    w.wdraw = c.take<uint32_t>(pad64(k));
+    w.parts = c.take<double>((k + COMBINE_BLOCK - 1) / COMBINE_BLOCK + 1024);
+    w.pos = c.take<uint32_t>(pad64(m));
+    ea = c.take<uint32_t>(pad64(k));
+    ex = c.take<uint32_t>(pad64(k));
+}
+
 // Weights, prefix sums and k draws over n items; returns BFC_E_PROBS for
 // invalid probabilities (reads the check back: synchronises).
 static int sample_draws(const double *d_probs, uint64_t n, uint64_t k, uint64_t seed,
@@ -1054,6 +1186,44 @@ int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t se
                                               (unsigned long long *)d_eids);
     BFC_HIP(hipGetLastError());
     return finish_estimate(k, m, (unsigned long long *)d_counts, d_probs != nullptr, w, d_est, s);
+}
+
+int bfc_esamp_fast_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    Carver c(nullptr, 0);
+    SampWs w;
+    uint32_t *ea, *ex;
+    carve_fast(c, g->n_edges, k, w, ea, ex);
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32_t alpha,
+                   uint64_t seed, uint64_t *d_eids, uint32_t *d_hits, double *d_est, void *d_ws,
+                   size_t ws_bytes, hipStream_t s) {
+    if (!g || !d_eids || !d_hits || !d_est || !d_ws) return BFC_E_NULL;
+    const uint64_t m = g->n_edges;
+    if (k == 0 || k > 0xFFFFFFFFull || alpha == 0 || m == 0) return BFC_E_ARG;
+    if (!aligned256(d_ws) || ((uintptr_t)d_eids & 7) || ((uintptr_t)d_hits & 3) ||
+        ((uintptr_t)d_est & 7))
+        return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    SampWs w;
+    uint32_t *ea, *ex;
+    carve_fast(c, m, k, w, ea, ex);
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    BFC_TRY(sample_draws(d_probs, m, k, seed, TAG_EDRAW, w, s));
+    k_pos_of_edge<<<grid_for(m), 256, 0, s>>>(g->eid_l, m, w.pos);
+    k_fast_setup<<<grid_for(k), 256, 0, s>>>(k, w.draw, w.pos, g->off_l, g->n_left, g->adj_l, ea,
+                                             ex, d_hits, (unsigned long long *)d_eids);
+    FastArgs f = {g->off_l, g->adj_l, g->off_r, g->adj_r, ea, ex, k, seed, alpha};
+    const uint64_t units = k * ((alpha + WAVE - 1) / WAVE);
+    const uint64_t blocks = (units + 3) / 4;
+    k_fast_trials<<<(unsigned)(blocks < 16384 ? blocks : 16384), 256, 0, s>>>(f, d_hits);
+    k_fast_combine<<<1, 256, 0, s>>>(f, m, d_hits, w.wdraw, d_probs ? w.pre : nullptr, w.parts,
+                                     d_est);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
 }
 
 }  // extern "C"
