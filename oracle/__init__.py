@@ -27,6 +27,8 @@ TAG_ESPAR = 0x45535052
 TAG_COLOR = 0x434C5253
 TAG_VDRAW = 0x56445257
 TAG_EDRAW = 0x45445257
+TAG_WDRAW = 0x57445257
+TAG_FAST = 0x46454243
 
 
 class OracleError(RuntimeError):
@@ -70,6 +72,8 @@ def lib():
         L.orc_esamp.argtypes = g + [dp, C.c_uint64, C.c_uint64, u64p, u64p, dp]
         L.orc_esamp_fast.argtypes = g + [dp, C.c_uint64, C.c_uint32, C.c_uint64, u64p, u32p, dp]
         L.orc_fast_ebfc_pairs.argtypes = g + [C.c_uint64, u64p]
+        L.orc_wsamp.argtypes = g + [C.c_uint64, C.c_uint64, u32p, u32p, u64p, dp]
+        L.orc_wedges.argtypes = g + [u64p, C.c_uint64, u32p, u32p, u64p, u64p]
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_philox4x32_10.restype = None
         L.orc_color.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
@@ -223,6 +227,34 @@ def fast_ebfc_pairs(nl, nr, l, r, e):
     out = C.c_uint64()
     _check(lib().orc_fast_ebfc_pairs(*_g(nl, nr, l, r), e, C.byref(out)))
     return out.value
+
+
+def wsamp(nl, nr, l, r, k, seed):
+    """WSamp (Sec. 5.3): returns (midpoints[k], ends[k, 2], counts[k], estimate); ids global."""
+    l, r = _edges(l, r)
+    mids = np.zeros(k, np.uint32)
+    ends = np.zeros((k, 2), np.uint32)
+    cnt = np.zeros(k, np.uint64)
+    est = C.c_double()
+    _check(lib().orc_wsamp(*_g(nl, nr, l, r), k, seed, _p(mids, C.c_uint32),
+                           _p(ends, C.c_uint32), _p(cnt, C.c_uint64), C.byref(est)))
+    return mids, ends, cnt, est.value
+
+
+def wedges(nl, nr, l, r, t=None):
+    """Decode wedge numbers t (default: all): (midpoints, ends, counts, W)."""
+    l, r = _edges(l, r)
+    W = C.c_uint64()
+    if t is None:
+        _check(lib().orc_wedges(*_g(nl, nr, l, r), None, 0, None, None, None, C.byref(W)))
+        t = np.arange(W.value, dtype=np.uint64)
+    t = np.ascontiguousarray(t, dtype=np.uint64)
+    mids = np.zeros(t.size, np.uint32)
+    ends = np.zeros((t.size, 2), np.uint32)
+    cnt = np.zeros(t.size, np.uint64)
+    _check(lib().orc_wedges(*_g(nl, nr, l, r), _p(t, C.c_uint64), t.size, _p(mids, C.c_uint32),
+                            _p(ends, C.c_uint32), _p(cnt, C.c_uint64), C.byref(W)))
+    return mids, ends, cnt, W.value
 
 
 def philox(ctr, key):

@@ -841,6 +841,125 @@ int orc_fast_ebfc_pairs(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l,
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------ */
+/* WSamp (Sec. 5.3): draw a wedge uniformly (its midpoint u with        */
+/* probability C(d_u,2) / W, then two distinct neighbours), count the   */
+/* butterflies through it, |G_v n G_w| - 1, and return beta * W / 4.    */
+/*                                                                      */
+/* Wedges are numbered 0 .. W-1: vertices in global order (L ids, then   */
+/* n_left + R id) take consecutive ranges of C(d_u,2) numbers; inside    */
+/* u's range, number p is the pair (j1, j2), j1 < j2, of positions in u's */
+/* neighbour list (ascending (degree, id) order of the other side) with  */
+/* p = C(j2,2) + j1 (pairs (0,1), (0,2), (1,2), (0,3), ...).  A uniform  */
+/* number is a uniform wedge, which is the lemma of Sec. 5.3.            */
+/* Draw i takes t = uniform_below(W) from the stream (i lo, i hi,        */
+/* TAG_WDRAW, attempt).  Estimate: ((double)sum beta * (double)W) /      */
+/* (4.0 * (double)k), the sum exact in uint64.                           */
+/* ------------------------------------------------------------------ */
+#define TAG_WDRAW 0x57445257u   /* wedge draw */
+
+typedef struct {
+    graph_t g;
+    fast_tmp_t t;
+    uint64_t n, W;
+    uint64_t *pre;      /* inclusive prefix sums of C(d,2) in global order */
+} wedges_t;
+
+static void wedges_free(wedges_t *w) {
+    free(w->pre); fast_tmp_free(&w->t); graph_free(&w->g);
+}
+
+static int wedges_init(wedges_t *w, uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l,
+                       const uint32_t *r) {
+    memset(w, 0, sizeof(*w));
+    int rc = graph_build(&w->g, nl, nr, m, l, r);
+    if (rc) return rc;
+    rc = fast_tmp_init(&w->t, &w->g);
+    if (rc) { graph_free(&w->g); return rc; }
+    w->n = (uint64_t)nl + nr;
+    w->pre = (uint64_t *)malloc((w->n ? w->n : 1) * 8);
+    if (!w->pre) { wedges_free(w); return ORC_E_NOMEM; }
+    uint64_t run = 0;
+    for (uint64_t v = 0; v < w->n; v++) {
+        uint64_t d = v < nl ? w->t.deg_l[v] : w->t.deg_r[v - nl];
+        run += choose2(d);
+        w->pre[v] = run;
+    }
+    w->W = run;
+    return ORC_OK;
+}
+
+static uint64_t common_neighbours(const adj_t *A, uint32_t v, uint32_t w) {
+    uint64_t i = A->off[v], ie = A->off[v + 1], j = A->off[w], je = A->off[w + 1], c = 0;
+    while (i < ie && j < je) {       /* merge of two id-sorted rows */
+        if (A->nbr[i] == A->nbr[j]) { c++; i++; j++; }
+        else if (A->nbr[i] < A->nbr[j]) i++;
+        else j++;
+    }
+    return c;
+}
+
+/* Wedge number t: midpoint (global id), endpoints (global ids, j1 then
+ * j2) and the butterflies through it. */
+static void wedge_of(wedges_t *w, uint64_t t, uint32_t *mid, uint32_t *e1, uint32_t *e2,
+                     uint64_t *beta) {
+    uint32_t nl = w->g.L.n;
+    uint64_t u = pick_weighted(w->pre, w->n, t);
+    uint64_t p = t - (u ? w->pre[u - 1] : 0);
+    uint64_t j2 = 1;
+    while (choose2(j2 + 1) <= p) j2++;
+    uint64_t j1 = p - choose2(j2);
+    *mid = (uint32_t)u;
+    if (u < nl) {                                   /* midpoint in L, ends in R */
+        list_by_degree(&w->g.L, (uint32_t)u, w->t.deg_r, w->t.nb_a);
+        uint32_t v = w->t.nb_a[j1], x = w->t.nb_a[j2];
+        *e1 = nl + v; *e2 = nl + x;
+        *beta = common_neighbours(&w->g.R, v, x) - 1;
+    } else {                                        /* midpoint in R, ends in L */
+        list_by_degree(&w->g.R, (uint32_t)(u - nl), w->t.deg_l, w->t.nb_a);
+        uint32_t v = w->t.nb_a[j1], x = w->t.nb_a[j2];
+        *e1 = v; *e2 = x;
+        *beta = common_neighbours(&w->g.L, v, x) - 1;
+    }
+}
+
+int orc_wsamp(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l, const uint32_t *r,
+              uint64_t k, uint64_t seed, uint32_t *mids, uint32_t *ends, uint64_t *counts,
+              double *est) {
+    if (k == 0 || !mids || !ends || !counts || !est) return ORC_E_ARG;
+    wedges_t w;
+    int rc = wedges_init(&w, nl, nr, m, l, r);
+    if (rc) return rc;
+    if (w.W == 0) { wedges_free(&w); return ORC_E_ARG; }
+    uint64_t s = 0;
+    for (uint64_t i = 0; i < k; i++) {
+        uint64_t t = uniform_below(seed, (uint32_t)i, (uint32_t)(i >> 32), TAG_WDRAW, w.W);
+        wedge_of(&w, t, &mids[i], &ends[2 * i], &ends[2 * i + 1], &counts[i]);
+        s += counts[i];
+    }
+    *est = ((double)s * (double)w.W) / (4.0 * (double)k);
+    wedges_free(&w);
+    return ORC_OK;
+}
+
+/* Decode wedge numbers t[0..cnt) (for tests that enumerate every wedge);
+ * *W receives the number of wedges. */
+int orc_wedges(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l, const uint32_t *r,
+               const uint64_t *t, uint64_t cnt, uint32_t *mids, uint32_t *ends, uint64_t *counts,
+               uint64_t *W) {
+    if (!W || (cnt && (!t || !mids || !ends || !counts))) return ORC_E_ARG;
+    wedges_t w;
+    int rc = wedges_init(&w, nl, nr, m, l, r);
+    if (rc) return rc;
+    *W = w.W;
+    for (uint64_t i = 0; i < cnt; i++) {
+        if (t[i] >= w.W) { wedges_free(&w); return ORC_E_ARG; }
+        wedge_of(&w, t[i], &mids[i], &ends[2 * i], &ends[2 * i + 1], &counts[i]);
+    }
+    wedges_free(&w);
+    return ORC_OK;
+}
+
 /* Raw draws only (for statistics tests that do not need the counts). */
 int orc_uniform_below(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag, uint64_t n,
                       uint64_t *out) {
