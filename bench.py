@@ -349,6 +349,97 @@ def bench_replicas(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_esamp_fast(args):
+    """Time to 1% error at 95% confidence of ESamp with Fast-eBFC (Sec. 5.5) on the
+    1M/5M/50M-edge graph, beside ESamp with exact per-edge counts and the exact count.
+
+    For each trial count alpha the variance of one draw's term is known in closed
+    form from the exact per-edge counts: (m/4)^2 mean_e(B_e^2 + B_e (d_a d_x - B_e)
+    / alpha) - B^2 (edge draw plus the binomial trials), which fixes the number of
+    draws k; the fastest (k, alpha) is then checked over seeded queries.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1801_00338_amd import api, gen
+
+    w = gen.WORKLOADS["chung_lu_1m_5m_50m"]
+    l, r = w.edges()
+    dev = torch.device("cuda:0")
+    g = api.Graph(w.nl, w.nr, l, r, device=dev)
+    m = l.size
+    dd = (np.bincount(l, minlength=w.nl).astype(np.float64)[l] *
+          np.bincount(r, minlength=w.nr).astype(np.float64)[r])
+    del l, r
+    B = g.exact()
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        g.exact()
+        ts.append(time.perf_counter() - t0)
+    exact_s = min(ts)
+    ce = g.per_edge().astype(np.float64)
+    log(f"B={B}, exact count {exact_s * 1e3:.1f} ms; per-edge counts read")
+    assert abs(ce.sum() / 4 - B) < 1e-6 * B
+
+    def k_for(v1):
+        return int(math.ceil((Z95 * math.sqrt(max(v1, 0.0)) / (0.01 * B)) ** 2))
+
+    def query_s(k, alpha, seeds=3):
+        bufs = g.esamp_fast_buffers(k)
+        g.esamp_fast_async(bufs, alpha, 1)
+        torch.cuda.synchronize(dev)
+        ts = []
+        for s in range(seeds):
+            t0 = time.perf_counter()
+            g.esamp_fast_async(bufs, alpha, 2 + s)
+            torch.cuda.synchronize(dev)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), bufs
+
+    cands = []
+    for alpha in (1, 4, 16, 64, 256, 1024):
+        v1 = (m / 4) ** 2 * float(np.mean(ce * ce + ce * (dd - ce) / alpha)) - float(B) ** 2
+        k = k_for(v1)
+        if k >= 2**31:
+            log(f"alpha={alpha}: k={k} too large")
+            continue
+        t, _ = query_s(k, alpha)
+        log(f"alpha={alpha}: sigma1={math.sqrt(v1):.4g} k={k} query {t * 1e3:.2f} ms")
+        cands.append((t, alpha, k, math.sqrt(v1)))
+    t, alpha, k, sig = min(cands)
+    bufs = g.esamp_fast_buffers(k)
+    errs, t0 = [], time.perf_counter()
+    for s in range(args.trials):
+        if time.perf_counter() - t0 > 60.0:
+            break
+        g.esamp_fast_async(bufs, alpha, (5 << 40) | s)
+        errs.append(abs(float(bufs["est"].item()) - B) / B)
+    p95 = float(np.percentile(errs, 95))
+    log(f"best alpha={alpha} k={k}: {t * 1e3:.2f} ms; p95 error {p95:.4f} over {len(errs)} seeds")
+    # ESamp with exact per-edge counts (Sec. 5.2) at its own k
+    v1e = (m / 4) ** 2 * float(np.mean(ce * ce)) - float(B) ** 2
+    ke = k_for(v1e)
+    t0 = time.perf_counter()
+    g.esamp(ke, 11)
+    esamp_s = time.perf_counter() - t0
+    log(f"ESamp with exact eBFC: k={ke}, {esamp_s * 1e3:.1f} ms")
+    line = {
+        "metric": "seconds to 1% error at 95% (ESamp with Fast-eBFC)", "value": t, "unit": "s",
+        "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": t * 1e3, "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "u32 hits, f64 estimate",
+        "data": "synthetic",
+        "config": dict(w.describe(), butterflies=B, alpha=alpha, k=k, sigma1=sig,
+                       p95_rel_err=p95, seeds=len(errs),
+                       step="edge draws, position map, alpha trials per draw, estimate"),
+        "esamp_exact_ebfc": {"k": ke, "s": esamp_s},
+        "exact_count_s": exact_s,
+        "candidates": [{"alpha": a_, "k": k_, "s": t_} for t_, a_, k_, _ in cands],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +479,8 @@ def main():
         return bench_batch(args)
     if args.workload == "replicas_256":
         return bench_replicas(args)
+    if args.workload == "esamp_fast":
+        return bench_esamp_fast(args)
     w = gen.WORKLOADS[args.workload]
     t0 = time.perf_counter()
     l, r = w.edges()
