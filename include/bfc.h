@@ -224,6 +224,24 @@ int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32
                    uint64_t seed, uint64_t *d_eids, uint32_t *d_hits, double *d_est,
                    void *d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* WSamp (Sec. 5.3): k < 2^32 draws with replacement of a uniform wedge, each
+ * counted exactly.  Wedges are numbered 0 .. W-1 (W = wedges_mid_l +
+ * wedges_mid_r): vertices in global order (L ids, then n_left + R id) own
+ * consecutive ranges of C(d,2) numbers, and number p of vertex u's range is
+ * the pair of positions (j1, j2), j1 < j2, p = C(j2,2) + j1, in u's
+ * neighbour list (ascending rank order).  Draw i takes a uniform number
+ * below W from the Philox stream (i lo, i hi, 'WDRW', attempt) by
+ * rejection.  d_mids[i] (uint32): the midpoint (global id); d_ends[2i],
+ * d_ends[2i+1] (uint32): the endpoints j1 and j2 (global ids); d_counts[i]
+ * (uint64): butterflies through the wedge, |G_v n G_w| - 1; *d_est =
+ * ((double)sum(counts) * (double)W) / (4.0 * (double)k), the sum exact in
+ * uint64.  BFC_E_ARG for k == 0, k >= 2^32 or a graph without wedges.
+ * Asynchronous. */
+int bfc_wsamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
+int bfc_wsamp(const bfc_graph *g, uint64_t k, uint64_t seed, uint32_t *d_mids, uint32_t *d_ends,
+              uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
+              hipStream_t stream);
+
 /* ---------------------------------------------------------------------- */
 /* Batched exact counts: many graphs counted in one persistent launch.      */
 /*                                                                          */

@@ -269,6 +269,35 @@ class Graph:
                 bufs["hits"].cpu().numpy().view(np.uint32)[:k].copy(),
                 float(bufs["est"].item()))
 
+    def wsamp_buffers(self, k):
+        """Device buffers for wsamp_async with k draws."""
+        sz = C.c_size_t()
+        check(lib().bfc_wsamp_ws_size(C.byref(self.g), k, C.byref(sz)), "wsamp ws size")
+        return dict(ws=_bytes(sz.value, self.device), k=k,
+                    mids=torch.zeros(max(k, 1), dtype=torch.int32, device=self.device),
+                    ends=torch.zeros(max(2 * k, 2), dtype=torch.int32, device=self.device),
+                    cnt=torch.zeros(max(k, 1), dtype=torch.int64, device=self.device),
+                    est=torch.zeros(1, dtype=torch.float64, device=self.device))
+
+    def wsamp_async(self, bufs, seed, stream=None):
+        """WSamp into ``bufs`` (from wsamp_buffers); no synchronisation."""
+        ws = bufs["ws"]
+        check(lib().bfc_wsamp(C.byref(self.g), bufs["k"], seed, C.c_void_p(bufs["mids"].data_ptr()),
+                              C.c_void_p(bufs["ends"].data_ptr()),
+                              C.c_void_p(bufs["cnt"].data_ptr()),
+                              C.c_void_p(bufs["est"].data_ptr()), C.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream(stream)), "wsamp")
+
+    def wsamp(self, k, seed):
+        """WSamp: (midpoints, ends (k, 2), counts, estimate); ids global (L, then n_left + R)."""
+        bufs = self.wsamp_buffers(k)
+        self.wsamp_async(bufs, seed)
+        torch.cuda.synchronize(self.device)
+        return (bufs["mids"].cpu().numpy().view(np.uint32)[:k].copy(),
+                bufs["ends"].cpu().numpy().view(np.uint32)[:2 * k].reshape(k, 2).copy(),
+                bufs["cnt"].cpu().numpy().view(np.uint64)[:k].copy(),
+                float(bufs["est"].item()))
+
     # -------------------------------------------------------------- batching
     def exact_tuned(self, tuning=None, side=BFC_SIDE_AUTO):
         """bfc_exact with a launch shape (a bfc_tuning, a dict of its fields, or None)."""

@@ -1,6 +1,7 @@
 // Estimators built on the exact and local counts (Sec. 5 and 6 of the paper):
 // edge sparsification (ESpar), colourful sparsification (ClrSpar), vertex
-// sampling (VSamp) and edge sampling (ESamp).
+// sampling (VSamp), edge sampling (ESamp, also with Fast-eBFC) and wedge
+// sampling (WSamp).
 //
 // Random decisions come from Philox-4x32-10 (Salmon, Moraes, Dror, Shaw,
 // SC'11) keyed by the 64-bit seed (key = seed low word, seed high word); each
@@ -17,6 +18,8 @@
 //                                x2 = out2 | out3 << 32, both rejected as above
 //                                (bounds d_x and d_a), neighbour picks x1 mod d_x
 //                                and x2 mod d_a in ascending rank order
+//   draw i of WSamp:             counter (i lo, i hi, 'WDRW', attempt), a wedge
+//                                number below W, rejected as above
 // Weighted draws quantise probabilities to integer weights
 // q_j = prob_j > 0 ? max(1, floor(prob_j / max(prob) * (2^32 - 1))) : 0 and
 // pick the first j whose inclusive prefix sum of q exceeds a uniform draw
@@ -32,6 +35,7 @@ constexpr uint32_t TAG_COLOR = 0x434C5253u;
 constexpr uint32_t TAG_VDRAW = 0x56445257u;
 constexpr uint32_t TAG_EDRAW = 0x45445257u;
 constexpr uint32_t TAG_FAST = 0x46454243u;
+constexpr uint32_t TAG_WDRAW = 0x57445257u;
 constexpr uint32_t COMBINE_BLOCK = 1024;   // draws summed left to right per block
 
 // ------------------------------------------------------------------ Philox
@@ -477,6 +481,122 @@ __global__ __launch_bounds__(256) void k_fast_combine(FastArgs f, uint64_t m, co
         double total = 0.0;
         for (uint64_t b = 0; b < nb; b++) total += parts[b];
         *est = total / ((double)f.k * (double)f.alpha);
+    }
+}
+
+// ------------------------------------------------------------------ WSamp
+// WSamp (Sec. 5.3).  Wedges are numbered 0 .. W-1: vertices in global order
+// (L ids, then n_left + R id) own consecutive ranges of C(d,2) numbers, and
+// number p inside u's range is the pair of neighbour positions (j1, j2),
+// j1 < j2, with p = C(j2,2) + j1 (neighbours in ascending rank order).  A
+// uniform number is a uniform wedge; its butterflies are |G_v n G_w| - 1.
+__device__ inline uint64_t choose2_u64(uint64_t d) { return d < 2 ? 0 : d * (d - 1) / 2; }
+
+__global__ void k_wedge_weights(uint32_t nl, uint32_t nr, const uint32_t *rank_l,
+                                const uint32_t *rank_r, const uint32_t *off_l,
+                                const uint32_t *off_r, unsigned long long *pre) {
+    const uint64_t n = (uint64_t)nl + nr;
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t d;
+        if (v < nl) {
+            const uint32_t rk = rank_l[v];
+            d = off_l[rk + 1] - off_l[rk];
+        } else {
+            const uint32_t rk = rank_r[v - nl];
+            d = off_r[rk + 1] - off_r[rk];
+        }
+        pre[v] = choose2_u64(d);
+    }
+}
+
+struct WsampArgs {
+    const uint32_t *off_l, *adj_l, *off_r, *adj_r, *rank_l, *rank_r, *id_l, *id_r;
+    const unsigned long long *pre;      // inclusive prefix sums of C(d,2), global order
+    uint64_t n, W, k, seed;
+    uint32_t nl;
+};
+
+// One wave per draw: every lane decodes the same wedge; the shorter
+// endpoint list is spread over the lanes and each entry is searched in the
+// longer one.
+__global__ __launch_bounds__(256) void k_wsamp(WsampArgs a, uint32_t *mids, uint32_t *ends,
+                                               unsigned long long *counts) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+    for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE; i < a.k;
+         i += nwaves) {
+        const uint64_t t = draw_below(a.seed, (uint32_t)i, (uint32_t)(i >> 32), TAG_WDRAW, a.W);
+        uint64_t lo = 0, hi = a.n;            // midpoint: first v with pre[v] > t
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (a.pre[mid] > t) hi = mid; else lo = mid + 1;
+        }
+        const uint64_t u = lo;
+        if (u >= a.n) {                       // totals disagree: report nothing, read nothing
+            if (lane == 0) {
+                mids[i] = 0xFFFFFFFFu;
+                ends[2 * i] = ends[2 * i + 1] = 0xFFFFFFFFu;
+                counts[i] = 0;
+            }
+            continue;
+        }
+        const uint64_t p = t - (u ? a.pre[u - 1] : 0);
+        // j2 = the largest j with C(j,2) <= p (a floating-point guess, then exact fixes)
+        uint64_t j2 = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+        while (j2 > 1 && choose2_u64(j2) > p) j2--;
+        while (choose2_u64(j2 + 1) <= p) j2++;
+        const uint64_t j1 = p - choose2_u64(j2);
+        const uint32_t *offB, *adjB;          // rows of the endpoints' side
+        uint32_t v, w, e1, e2;
+        if (u < a.nl) {
+            const uint32_t base = a.off_l[a.rank_l[u]];
+            v = a.adj_l[base + j1];
+            w = a.adj_l[base + j2];
+            e1 = a.nl + a.id_r[v];
+            e2 = a.nl + a.id_r[w];
+            offB = a.off_r;
+            adjB = a.adj_r;
+        } else {
+            const uint32_t base = a.off_r[a.rank_r[u - a.nl]];
+            v = a.adj_r[base + j1];
+            w = a.adj_r[base + j2];
+            e1 = a.id_l[v];
+            e2 = a.id_l[w];
+            offB = a.off_l;
+            adjB = a.adj_l;
+        }
+        const uint32_t lv = offB[v], dv = offB[v + 1] - lv;
+        const uint32_t lw = offB[w], dw = offB[w + 1] - lw;
+        const uint32_t ls = dv <= dw ? lv : lw, ds = dv <= dw ? dv : dw;
+        const uint32_t lb = dv <= dw ? lw : lv, db = dv <= dw ? dw : dv;
+        uint64_t c = 0;
+        for (uint32_t b0 = 0; b0 < ds; b0 += WAVE) {
+            const uint32_t idx = b0 + lane;
+            const bool found = idx < ds && in_sorted(adjB + lb, db, adjB[ls + idx]);
+            c += (uint64_t)__popcll(__ballot(found));
+        }
+        if (lane == 0) {
+            mids[i] = (uint32_t)u;
+            ends[2 * i] = e1;
+            ends[2 * i + 1] = e2;
+            counts[i] = c - 1;                // the midpoint itself is common
+        }
+    }
+}
+
+// Estimate: ((double)sum counts * (double)W) / (4 k), the sum exact in uint64.
+__global__ __launch_bounds__(256) void k_wsamp_combine(uint64_t k, double W,
+                                                       const unsigned long long *counts,
+                                                       unsigned long long *parts, double *est) {
+    unsigned long long s = 0;
+    for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) s += counts[i];
+    parts[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (unsigned j = 0; j < blockDim.x; j++) t += parts[j];
+        *est = ((double)t * W) / (4.0 * (double)k);
     }
 }
 
@@ -1066,6 +1186,14 @@ static void carve_fast(Carver &c, uint64_t m, uint64_t k, SampWs &w, uint32_t *&
     ex = c.take<uint32_t>(pad64(k));
 }
 
+// WSamp: prefix sums of C(d,2) over the n vertices, scan scratch, partial sums.
+static void carve_wsamp(Carver &c, uint64_t n, unsigned long long *&pre,
+                        unsigned long long *&tmp, unsigned long long *&parts) {
+    pre = c.take<unsigned long long>(pad64(n));
+    tmp = c.take<unsigned long long>((n + S64_TILE - 1) / S64_TILE + 64);
+    parts = c.take<unsigned long long>(256);
+}
+
 // Weights, prefix sums and k draws over n items; returns BFC_E_PROBS for
 // invalid probabilities (reads the check back: synchronises).
 static int sample_draws(const double *d_probs, uint64_t n, uint64_t k, uint64_t seed,
@@ -1222,6 +1350,44 @@ int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32
     k_fast_trials<<<(unsigned)(blocks < 16384 ? blocks : 16384), 256, 0, s>>>(f, d_hits);
     k_fast_combine<<<1, 256, 0, s>>>(f, m, d_hits, w.wdraw, d_probs ? w.pre : nullptr, w.parts,
                                      d_est);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+int bfc_wsamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    Carver c(nullptr, 0);
+    unsigned long long *pre, *tmp, *parts;
+    carve_wsamp(c, (uint64_t)g->n_left + g->n_right, pre, tmp, parts);
+    (void)k;
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_wsamp(const bfc_graph *g, uint64_t k, uint64_t seed, uint32_t *d_mids, uint32_t *d_ends,
+              uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!g || !d_mids || !d_ends || !d_counts || !d_est || !d_ws) return BFC_E_NULL;
+    const uint64_t n = (uint64_t)g->n_left + g->n_right;
+    const uint64_t W = g->wedges_mid_l + g->wedges_mid_r;
+    if (k == 0 || k > 0xFFFFFFFFull || W == 0) return BFC_E_ARG;
+    if (!aligned256(d_ws) || ((uintptr_t)d_counts & 7) || ((uintptr_t)d_est & 7) ||
+        ((uintptr_t)d_mids & 3) || ((uintptr_t)d_ends & 3))
+        return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    unsigned long long *pre, *tmp, *parts;
+    carve_wsamp(c, n, pre, tmp, parts);
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    k_wedge_weights<<<grid_for(n), 256, 0, s>>>(g->n_left, g->n_right, g->rank_l, g->rank_r,
+                                                g->off_l, g->off_r, pre);
+    BFC_HIP(hipGetLastError());
+    BFC_TRY(scan_u64_inclusive(pre, n, tmp, s));
+    WsampArgs a = {g->off_l, g->adj_l, g->off_r, g->adj_r, g->rank_l, g->rank_r, g->id_l,
+                   g->id_r, pre, n, W, k, seed, g->n_left};
+    const uint64_t blocks = (k + 3) / 4;
+    k_wsamp<<<(unsigned)(blocks < 16384 ? blocks : 16384), 256, 0, s>>>(
+        a, d_mids, d_ends, (unsigned long long *)d_counts);
+    k_wsamp_combine<<<1, 256, 0, s>>>(k, (double)W, (const unsigned long long *)d_counts, parts,
+                                      d_est);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
