@@ -425,6 +425,47 @@ def bench_esamp_fast(args):
     g.esamp(ke, 11)
     esamp_s = time.perf_counter() - t0
     log(f"ESamp with exact eBFC: k={ke}, {esamp_s * 1e3:.1f} ms")
+    # WSamp (Sec. 5.3): sigma1 from a pilot of 4M draws, then the query at its k
+    Wt = g.g.wedges_mid_l + g.g.wedges_mid_r
+    pilot = g.wsamp_buffers(4_000_000)
+    g.wsamp_async(pilot, 3)
+    torch.cuda.synchronize(dev)
+    sig_w = (Wt / 4) * float(pilot["cnt"].double().std())
+    del pilot
+    kw = k_for(sig_w ** 2)
+    bw = g.wsamp_buffers(kw)
+    g.wsamp_async(bw, 4)
+    torch.cuda.synchronize(dev)
+    tw = []
+    for s_ in range(3):
+        t0 = time.perf_counter()
+        g.wsamp_async(bw, 5 + s_)
+        torch.cuda.synchronize(dev)
+        tw.append(time.perf_counter() - t0)
+    errs_w, t0 = [], time.perf_counter()
+    for s_ in range(args.trials):
+        if time.perf_counter() - t0 > 30.0:
+            break
+        g.wsamp_async(bw, (5 << 40) | s_)
+        errs_w.append(abs(float(bw["est"].item()) - B) / B)
+    del bw
+    wsamp = {"k": kw, "s": float(np.median(tw)), "sigma1_pilot": sig_w,
+             "p95_rel_err": float(np.percentile(errs_w, 95)), "seeds": len(errs_w)}
+    log(f"WSamp: {wsamp}")
+    # VSamp (Sec. 5.1), uniform: closed-form k from the exact per-vertex counts
+    cl, cr = g.per_vertex()
+    cv = np.concatenate([cl, cr]).astype(np.float64)
+    kv = k_for(cv.size * float(np.dot(cv, cv)) / 16 - float(B) ** 2)
+    kvt = min(kv, 1_000_000)
+    bv = g.vsamp_buffers(kvt)
+    g.vsamp_async(bv, 1)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    g.vsamp_async(bv, 2)
+    torch.cuda.synchronize(dev)
+    vsamp = {"k": kv, "timed_k": kvt, "s_at_timed_k": time.perf_counter() - t0}
+    del bv
+    log(f"VSamp uniform: {vsamp}")
     line = {
         "metric": "seconds to 1% error at 95% (ESamp with Fast-eBFC)", "value": t, "unit": "s",
         "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": t * 1e3, "higher_is_better": False,
@@ -434,8 +475,72 @@ def bench_esamp_fast(args):
                        p95_rel_err=p95, seeds=len(errs),
                        step="edge draws, position map, alpha trials per draw, estimate"),
         "esamp_exact_ebfc": {"k": ke, "s": esamp_s},
+        "wsamp": wsamp,
+        "vsamp_uniform": vsamp,
         "exact_count_s": exact_s,
         "candidates": [{"alpha": a_, "k": k_, "s": t_} for t_, a_, k_, _ in cands],
+    }
+    print(json.dumps(line), flush=True)
+
+
+SIDE_GRAPHS = [   # (|L|, |R|, gamma_L, gamma_R), 10M edges each, expected degrees capped at 100k
+    (1_000_000, 5_000_000, 2.1, 2.3), (5_000_000, 1_000_000, 2.3, 2.1),
+    (2_000_000, 2_000_000, 2.1, 2.8), (2_000_000, 2_000_000, 2.8, 2.1),
+    (2_000_000, 2_000_000, 2.5, 2.5), (500_000, 10_000_000, 2.4, 2.4),
+]
+
+
+def bench_side_ablation(args):
+    """Exact count from L, from R and by the paper's rule (Sec. 4: start from R iff
+    sum_L d^2 < sum_R d^2) on synthetic graphs across skews and side ratios: the
+    time follows the wedges of the chosen start side, and the rule picks the side
+    with fewer of them."""
+    import torch
+
+    from paper_1801_00338_amd import api, gen
+    from paper_1801_00338_amd._lib import BFC_SIDE_AUTO, BFC_SIDE_L, BFC_SIDE_R
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for j, (nl, nr, gl, gr) in enumerate(SIDE_GRAPHS):
+        l, r = gen.chung_lu(nl, nr, 10_000_000, gl, gr, 100_000, seed=(7 << 32) | j)
+        g = api.Graph(nl, nr, l, r, device=dev)
+        del l, r
+        out = torch.zeros(1, dtype=torch.int64, device=dev)
+        row = {"n_left": nl, "n_right": nr, "gamma_left": gl, "gamma_right": gr,
+               "sumsq_left": g.g.sumsq_l, "sumsq_right": g.g.sumsq_r,
+               "auto_side": "R" if g.side_used(BFC_SIDE_AUTO) == BFC_SIDE_R else "L"}
+        counts = set()
+        for name, side in (("L", BFC_SIDE_L), ("R", BFC_SIDE_R), ("auto", BFC_SIDE_AUTO)):
+            g.exact_async(out, side)
+            torch.cuda.synchronize(dev)
+            counts.add(int(out.item()))
+            ts = []
+            for _ in range(max(1, args.steps)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                g.exact_async(out, side)
+                e1.record()
+                torch.cuda.synchronize(dev)
+                ts.append(e0.elapsed_time(e1))
+            row[f"ms_{name}"] = min(ts)
+            if name != "auto":
+                row[f"wedges_{name}"] = g.wedges(side)
+        assert len(counts) == 1, "the count must not depend on the side"
+        row["butterflies"] = counts.pop()
+        row["auto_is_faster_side"] = row["ms_auto"] <= 1.05 * min(row["ms_L"], row["ms_R"])
+        log(json.dumps(row))
+        rows.append(row)
+        del g
+        torch.cuda.empty_cache()
+    worst = max(max(r_["ms_L"], r_["ms_R"]) / r_["ms_auto"] for r_ in rows)
+    line = {
+        "metric": "slowdown of the wrong start side over the paper's side choice (max)",
+        "value": worst, "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": sum(r_["ms_auto"] for r_ in rows), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "side_ablation (6 Chung-Lu graphs of 10M edges)",
+                   "graphs": rows},
     }
     print(json.dumps(line), flush=True)
 
@@ -479,7 +584,9 @@ def main():
         return bench_batch(args)
     if args.workload == "replicas_256":
         return bench_replicas(args)
-    if args.workload == "esamp_fast":
+    if args.workload == "side_ablation":
+        return bench_side_ablation(args)
+    if args.workload in ("esamp_fast", "samplers"):
         return bench_esamp_fast(args)
     w = gen.WORKLOADS[args.workload]
     t0 = time.perf_counter()
