@@ -242,6 +242,29 @@ int bfc_wsamp(const bfc_graph *g, uint64_t k, uint64_t seed, uint32_t *d_mids, u
               uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
               hipStream_t stream);
 
+/* (eps, delta) estimates from the sparsifiers (Sec. 6.1, 6.2).
+ * bfc_spar_threshold (host): the sampling rate of the ESpar lemma,
+ * p = min(1, max((24/B)^(1/4), sqrt(24 D / B), 24 D^2 / B)), or for ClrSpar
+ * the largest number of colours N with 1/N > max((32/B)^(1/3),
+ * sqrt(32 D / B), 32 D^2 / B) (at least 1; *p = 1/N), from an estimate B of
+ * the count (a pilot, e.g. bfc_esamp_fast) and the largest degree D.
+ * kind: BFC_REPLICA_ESPAR or BFC_REPLICA_CLRSPAR.  B <= 0 keeps everything.
+ * bfc_eps_delta_plan (host): g groups of r estimates, r = ceil(3 / (2
+ * eps^2)), g = ceil(8 ln(1/delta)) made odd.  Above the thresholds one
+ * estimate's variance is below 3 B^2 / 8 (the lemmas' argument with
+ * butterfly pairs counted in both orders and per-butterfly pair bounds), so
+ * a group mean misses B by more than eps B with probability at most 1/4
+ * (Chebyshev) and the median of the g means with probability at most
+ * exp(-g/8) <= delta (Hoeffding).  BFC_E_ARG unless 0 < eps <= 1,
+ * 0 < delta < 1 and g <= 4096.
+ * bfc_median_of_means (device): d_x holds groups * per_group doubles, group
+ * q at [q r, q r + r); d_means[q] = (sum left to right) / r; *d_median = the
+ * mean at sorted position (g - 1) / 2.  Asynchronous. */
+int bfc_spar_threshold(int kind, double B, uint32_t max_deg, double *p, uint32_t *ncolors);
+int bfc_eps_delta_plan(double eps, double delta, uint32_t *groups, uint32_t *per_group);
+int bfc_median_of_means(const double *d_x, uint32_t groups, uint32_t per_group, double *d_means,
+                        double *d_median, hipStream_t stream);
+
 /* ---------------------------------------------------------------------- */
 /* Batched exact counts: many graphs counted in one persistent launch.      */
 /*                                                                          */

@@ -115,6 +115,12 @@ SIGNATURES = {
     "bfc_wsamp_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
     "bfc_wsamp": ([C.POINTER(bfc_graph), C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_spar_threshold": ([C.c_int, C.c_double, C.c_uint32, C.POINTER(C.c_double),
+                            C.POINTER(C.c_uint32)], C.c_int),
+    "bfc_eps_delta_plan": ([C.c_double, C.c_double, C.POINTER(C.c_uint32),
+                            C.POINTER(C.c_uint32)], C.c_int),
+    "bfc_median_of_means": ([C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
+                             C.c_void_p], C.c_int),
     "bfc_exact_tuned": ([C.POINTER(bfc_graph), C.c_int, C.POINTER(bfc_tuning), C.c_void_p,
                          C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bfc_exact_parts_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),

@@ -298,6 +298,28 @@ class Graph:
                 bufs["cnt"].cpu().numpy().view(np.uint64)[:k].copy(),
                 float(bufs["est"].item()))
 
+    def spar_eps_delta(self, kind, eps, delta, seed, B_pilot, log=None):
+        """(eps, delta) estimate from ESpar or ClrSpar replicas (Sec. 6.1, 6.2): the lemma's
+        rate from a pilot count and the largest degree, g groups of r replicas (replica i
+        seeded seed + i) counted in one batch, the median of the group means.
+        Returns (median, group means, p or N, g, r)."""
+        kind_id = _lib.BFC_REPLICA_ESPAR if kind == "espar" else _lib.BFC_REPLICA_CLRSPAR
+        p, nc = C.c_double(), C.c_uint32()
+        check(lib().bfc_spar_threshold(kind_id, float(B_pilot),
+                                       max(self.g.max_deg_l, self.g.max_deg_r),
+                                       C.byref(p), C.byref(nc)), "threshold")
+        g, r = C.c_uint32(), C.c_uint32()
+        check(lib().bfc_eps_delta_plan(eps, delta, C.byref(g), C.byref(r)), "plan")
+        g, r = g.value, r.value
+        param = p.value if kind == "espar" else nc.value
+        _, est, _ = self.spar_batch([(kind, param, seed + i) for i in range(g * r)], log=log)
+        x = torch.as_tensor(np.ascontiguousarray(est, dtype=np.float64)).to(self.device)
+        means = torch.zeros(g, dtype=torch.float64, device=self.device)
+        med = torch.zeros(1, dtype=torch.float64, device=self.device)
+        median_of_means(x, g, r, means, med)
+        torch.cuda.synchronize(self.device)
+        return float(med.item()), means.cpu().numpy(), param, g, r
+
     # -------------------------------------------------------------- batching
     def exact_tuned(self, tuning=None, side=BFC_SIDE_AUTO):
         """bfc_exact with a launch shape (a bfc_tuning, a dict of its fields, or None)."""
@@ -362,6 +384,15 @@ class Graph:
 
     def per_edge(self):
         return self.local(vertices=False, edges=True)[2]
+
+
+def median_of_means(x, groups, per_group, means, median, stream=None):
+    """bfc_median_of_means on device float64 tensors (x: groups * per_group values)."""
+    if x.numel() < groups * per_group or means.numel() < groups:
+        raise ValueError("buffers too small")
+    check(lib().bfc_median_of_means(C.c_void_p(x.data_ptr()), groups, per_group,
+                                    C.c_void_p(means.data_ptr()), C.c_void_p(median.data_ptr()),
+                                    _stream(stream)), "median of means")
 
 
 def _tuning(t):

@@ -457,30 +457,39 @@ __global__ __launch_bounds__(256) void k_fast_trials(FastArgs f, uint32_t *hits)
 // Estimate: term_i = ((double)hits_i * (double)(d_a d_x)) * s_i with s_i =
 // m / 4 (uniform) or Q / (4 q_i) (weighted), summed left to right within
 // blocks of COMBINE_BLOCK draws, block sums left to right, over k * alpha.
-__global__ __launch_bounds__(256) void k_fast_combine(FastArgs f, uint64_t m, const uint32_t *hits,
-                                                      const uint32_t *wdraw,
-                                                      const unsigned long long *pre,
-                                                      double *parts, double *est) {
-    const uint64_t nb = (f.k + COMBINE_BLOCK - 1) / COMBINE_BLOCK;
+// The terms are formed in parallel, each block's sum by one thread, the
+// total by one thread: the same additions in the same order.
+__global__ void k_fast_terms(FastArgs f, uint64_t m, const uint32_t *hits, const uint32_t *wdraw,
+                             const unsigned long long *pre, double *terms) {
     const double su = (double)m / 4.0;
     const double Q = pre ? (double)pre[m - 1] : 0.0;
-    for (uint64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < f.k;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = f.ea[i], x = f.ex[i];
+        const uint64_t dd = (uint64_t)(f.off_l[a + 1] - f.off_l[a]) *
+                            (f.off_r[x + 1] - f.off_r[x]);
+        const double sc = pre ? Q / (4.0 * (double)wdraw[i]) : su;
+        terms[i] = ((double)hits[i] * (double)dd) * sc;
+    }
+}
+
+__global__ void k_block_sums(const double *terms, uint64_t k, double *parts) {
+    const uint64_t nb = (k + COMBINE_BLOCK - 1) / COMBINE_BLOCK;
+    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < nb;
+         b += (uint64_t)gridDim.x * blockDim.x) {
         double part = 0.0;
-        const uint64_t e = min((uint64_t)(b + 1) * COMBINE_BLOCK, f.k);
-        for (uint64_t i = b * COMBINE_BLOCK; i < e; i++) {
-            const uint32_t a = f.ea[i], x = f.ex[i];
-            const uint64_t dd = (uint64_t)(f.off_l[a + 1] - f.off_l[a]) *
-                                (f.off_r[x + 1] - f.off_r[x]);
-            const double sc = pre ? Q / (4.0 * (double)wdraw[i]) : su;
-            part += ((double)hits[i] * (double)dd) * sc;
-        }
+        const uint64_t e = min((uint64_t)(b + 1) * COMBINE_BLOCK, k);
+        for (uint64_t i = b * COMBINE_BLOCK; i < e; i++) part += terms[i];
         parts[b] = part;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+}
+
+__global__ void k_fast_total(uint64_t k, uint32_t alpha, const double *parts, double *est) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint64_t nb = (k + COMBINE_BLOCK - 1) / COMBINE_BLOCK;
         double total = 0.0;
         for (uint64_t b = 0; b < nb; b++) total += parts[b];
-        *est = total / ((double)f.k * (double)f.alpha);
+        *est = total / ((double)k * (double)alpha);
     }
 }
 
@@ -585,18 +594,50 @@ __global__ __launch_bounds__(256) void k_wsamp(WsampArgs a, uint32_t *mids, uint
     }
 }
 
-// Estimate: ((double)sum counts * (double)W) / (4 k), the sum exact in uint64.
-__global__ __launch_bounds__(256) void k_wsamp_combine(uint64_t k, double W,
-                                                       const unsigned long long *counts,
-                                                       unsigned long long *parts, double *est) {
+// Estimate: ((double)sum counts * (double)W) / (4 k), the sum exact in uint64
+// (integer additions: any order gives the same sum).
+__global__ void k_zero_u64(unsigned long long *p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = 0;
+}
+
+__global__ __launch_bounds__(256) void k_wsamp_sum(uint64_t k, const unsigned long long *counts,
+                                                   unsigned long long *acc) {
+    __shared__ unsigned long long red[256 / WAVE];
     unsigned long long s = 0;
-    for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) s += counts[i];
-    parts[threadIdx.x] = s;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < k;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        s += counts[i];
+    s = block_sum64<256>(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(acc, s);
+}
+
+__global__ void k_wsamp_est(uint64_t k, double W, const unsigned long long *acc, double *est) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *est = ((double)*acc * W) / (4.0 * (double)k);
+}
+
+// ------------------------------------------------------------------ (eps, delta)
+// Median of means: group q holds x[q r .. q r + r), its mean sums left to
+// right and divides by r; the median is the mean of sorted position
+// (g - 1) / 2, ties broken by group index.
+constexpr uint32_t MOM_MAX_GROUPS = 4096;
+
+__global__ __launch_bounds__(256) void k_median_of_means(const double *x, uint32_t g, uint32_t r,
+                                                         double *means, double *median) {
+    for (uint32_t q = threadIdx.x; q < g; q += blockDim.x) {
+        double s = 0.0;
+        for (uint32_t i = 0; i < r; i++) s += x[(uint64_t)q * r + i];
+        means[q] = s / (double)r;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (unsigned j = 0; j < blockDim.x; j++) t += parts[j];
-        *est = ((double)t * W) / (4.0 * (double)k);
+    const uint32_t mid = (g - 1) / 2;
+    for (uint32_t q = threadIdx.x; q < g; q += blockDim.x) {
+        const double mq = means[q];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < g; j++) {
+            const double mj = means[j];
+            rank += (mj < mq) || (mj == mq && j < q);
+        }
+        if (rank == mid) *median = mq;
     }
 }
 
@@ -1172,7 +1213,7 @@ static int carve_samp(Carver &c, const bfc_graph *g, uint64_t n, uint64_t k, int
 // Fast-eBFC sampler: the draw buffers of carve_samp, the edge position map
 // and the per-draw endpoints.
 static void carve_fast(Carver &c, uint64_t m, uint64_t k, SampWs &w, uint32_t *&ea,
-                       uint32_t *&ex) {
+                       uint32_t *&ex, double *&terms) {
     w = SampWs{};
     w.flags = c.take<ProbFlags>(1);
     w.w = c.take<unsigned long long>(pad64(m));
@@ -1184,6 +1225,7 @@ static void carve_fast(Carver &c, uint64_t m, uint64_t k, SampWs &w, uint32_t *&
     w.pos = c.take<uint32_t>(pad64(m));
     ea = c.take<uint32_t>(pad64(k));
     ex = c.take<uint32_t>(pad64(k));
+    terms = c.take<double>(pad64(k));
 }
 
 // WSamp: prefix sums of C(d,2) over the n vertices, scan scratch, partial sums.
@@ -1321,7 +1363,8 @@ int bfc_esamp_fast_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
     Carver c(nullptr, 0);
     SampWs w;
     uint32_t *ea, *ex;
-    carve_fast(c, g->n_edges, k, w, ea, ex);
+    double *terms;
+    carve_fast(c, g->n_edges, k, w, ea, ex, terms);
     *bytes = c.used;
     return BFC_OK;
 }
@@ -1338,7 +1381,8 @@ int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32
     Carver c(d_ws, ws_bytes);
     SampWs w;
     uint32_t *ea, *ex;
-    carve_fast(c, m, k, w, ea, ex);
+    double *terms;
+    carve_fast(c, m, k, w, ea, ex, terms);
     if (!c.fits()) return BFC_E_WS_SMALL;
     BFC_TRY(sample_draws(d_probs, m, k, seed, TAG_EDRAW, w, s));
     k_pos_of_edge<<<grid_for(m), 256, 0, s>>>(g->eid_l, m, w.pos);
@@ -1348,8 +1392,11 @@ int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32
     const uint64_t units = k * ((alpha + WAVE - 1) / WAVE);
     const uint64_t blocks = (units + 3) / 4;
     k_fast_trials<<<(unsigned)(blocks < 16384 ? blocks : 16384), 256, 0, s>>>(f, d_hits);
-    k_fast_combine<<<1, 256, 0, s>>>(f, m, d_hits, w.wdraw, d_probs ? w.pre : nullptr, w.parts,
-                                     d_est);
+    k_fast_terms<<<grid_for(k), 256, 0, s>>>(f, m, d_hits, w.wdraw, d_probs ? w.pre : nullptr,
+                                             terms);
+    k_block_sums<<<grid_for((k + COMBINE_BLOCK - 1) / COMBINE_BLOCK, 64), 64, 0, s>>>(terms, k,
+                                                                                  w.parts);
+    k_fast_total<<<1, 64, 0, s>>>(k, alpha, w.parts, d_est);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
@@ -1386,8 +1433,66 @@ int bfc_wsamp(const bfc_graph *g, uint64_t k, uint64_t seed, uint32_t *d_mids, u
     const uint64_t blocks = (k + 3) / 4;
     k_wsamp<<<(unsigned)(blocks < 16384 ? blocks : 16384), 256, 0, s>>>(
         a, d_mids, d_ends, (unsigned long long *)d_counts);
-    k_wsamp_combine<<<1, 256, 0, s>>>(k, (double)W, (const unsigned long long *)d_counts, parts,
-                                      d_est);
+    k_zero_u64<<<1, 64, 0, s>>>(parts);
+    const uint64_t sb = (k + 255) / 256;
+    k_wsamp_sum<<<(unsigned)(sb < 2048 ? sb : 2048), 256, 0, s>>>(
+        k, (const unsigned long long *)d_counts, parts);
+    k_wsamp_est<<<1, 64, 0, s>>>(k, (double)W, parts, d_est);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+int bfc_spar_threshold(int kind, double B, uint32_t max_deg, double *p, uint32_t *ncolors) {
+    if (!p || !ncolors) return BFC_E_NULL;
+    if (!(B == B)) return BFC_E_ARG;
+    const double D = (double)max_deg;
+    *p = 1.0;
+    *ncolors = 1;
+    if (kind == BFC_REPLICA_ESPAR) {
+        if (B <= 0.0) return BFC_OK;
+        double b = pow(24.0 / B, 0.25);
+        b = fmax(b, sqrt(24.0 * D / B));
+        b = fmax(b, 24.0 * D * D / B);
+        *p = b < 1.0 ? b : 1.0;
+        return BFC_OK;
+    }
+    if (kind == BFC_REPLICA_CLRSPAR) {
+        if (B <= 0.0) return BFC_OK;
+        double b = pow(32.0 / B, 1.0 / 3.0);
+        b = fmax(b, sqrt(32.0 * D / B));
+        b = fmax(b, 32.0 * D * D / B);
+        if (b >= 1.0) return BFC_OK;
+        double f = floor(1.0 / b);            // then the largest N with 1/N > b
+        uint64_t n = f > 4294967295.0 ? 4294967295ull : (uint64_t)f;
+        if (n < 1) n = 1;
+        while (n > 1 && !(1.0 / (double)n > b)) n--;
+        while (n < 4294967295ull && 1.0 / (double)(n + 1) > b) n++;
+        *ncolors = (uint32_t)n;
+        *p = 1.0 / (double)n;
+        return BFC_OK;
+    }
+    return BFC_E_ARG;
+}
+
+int bfc_eps_delta_plan(double eps, double delta, uint32_t *groups, uint32_t *per_group) {
+    if (!groups || !per_group) return BFC_E_NULL;
+    if (!(eps > 0.0 && eps <= 1.0) || !(delta > 0.0 && delta < 1.0)) return BFC_E_ARG;
+    const double r = ceil(3.0 / (2.0 * eps * eps));
+    double g = ceil(8.0 * log(1.0 / delta));
+    if (fmod(g, 2.0) == 0.0) g += 1.0;
+    if (r > 4294967295.0 || g > (double)MOM_MAX_GROUPS) return BFC_E_ARG;
+    *groups = (uint32_t)g;
+    *per_group = (uint32_t)r;
+    return BFC_OK;
+}
+
+int bfc_median_of_means(const double *d_x, uint32_t groups, uint32_t per_group, double *d_means,
+                        double *d_median, hipStream_t s) {
+    if (!d_x || !d_means || !d_median) return BFC_E_NULL;
+    if (groups == 0 || per_group == 0 || groups > MOM_MAX_GROUPS) return BFC_E_ARG;
+    if (((uintptr_t)d_x & 7) || ((uintptr_t)d_means & 7) || ((uintptr_t)d_median & 7))
+        return BFC_E_ALIGN;
+    k_median_of_means<<<1, 256, 0, s>>>(d_x, groups, per_group, d_means, d_median);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
