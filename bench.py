@@ -350,8 +350,9 @@ def bench_replicas(args):
 
 
 def bench_esamp_fast(args):
-    """Time to 1% error at 95% confidence of ESamp with Fast-eBFC (Sec. 5.5) on the
-    1M/5M/50M-edge graph, beside ESamp with exact per-edge counts and the exact count.
+    """Time to 1% error at 95% confidence of ESamp with Fast-eBFC (Sec. 5.5) on one graph
+    (default: the 1M/5M/50M-edge one), beside WSamp, ESamp with exact per-edge counts,
+    uniform VSamp and the exact count.
 
     For each trial count alpha the variance of one draw's term is known in closed
     form from the exact per-edge counts: (m/4)^2 mean_e(B_e^2 + B_e (d_a d_x - B_e)
@@ -363,8 +364,10 @@ def bench_esamp_fast(args):
 
     from paper_1801_00338_amd import api, gen
 
-    w = gen.WORKLOADS["chung_lu_1m_5m_50m"]
+    w = gen.WORKLOADS[args.sampler_graph]
+    t0 = time.perf_counter()
     l, r = w.edges()
+    log(f"generated {w.name} in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     g = api.Graph(w.nl, w.nr, l, r, device=dev)
     m = l.size
@@ -551,6 +554,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="chung_lu_1m_5m_50m")
+    ap.add_argument("--sampler-graph", default="chung_lu_1m_5m_50m",
+                    help="graph of --workload samplers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-learned", action="store_true",
