@@ -416,8 +416,54 @@ __device__ inline bool in_sorted(const uint32_t *a, uint32_t n, uint32_t t) {
     return lo < n && a[lo] == t;
 }
 
-// One wave per (draw, 64 consecutive trials); a wave adds its hits to the
-// draw's counter with one atomic.
+// One trial's probe: lower bound of `target` in row[lo..hi), with `found`
+// set when a probe equals it (the lower bound is always probed before the
+// search ends, so no final load is needed).  Lanes without a probe (a miss
+// already decided, or no trial) get an empty search.
+struct Probe {
+    const uint32_t *row;
+    uint32_t lo, hi, target;
+    bool found;
+};
+
+__device__ inline Probe trial_probe(const FastArgs &f, uint64_t i, uint32_t j, bool valid) {
+    Probe t = {f.adj_l, 0, 0, 0, false};
+    if (!valid) return t;
+    const uint32_t a = f.ea[i], x = f.ex[i];
+    const uint32_t la = f.off_l[a], da = f.off_l[a + 1] - la;
+    const uint32_t lx = f.off_r[x], dx = f.off_r[x + 1] - lx;
+    const uint64_t rx = (0 - (uint64_t)dx) % dx, ra = (0 - (uint64_t)da) % da;
+    uint32_t o[4];
+    uint64_t x1, x2;
+    for (uint32_t attempt = 0;; attempt++) {
+        philox((uint32_t)i, j, TAG_FAST, attempt, f.seed, o);
+        x1 = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+        x2 = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+        if ((rx == 0 || x1 < 0 - rx) && (ra == 0 || x2 < 0 - ra)) break;
+    }
+    const uint32_t b = f.adj_r[lx + (uint32_t)(x1 % dx)];   // L rank
+    const uint32_t y = f.adj_l[la + (uint32_t)(x2 % da)];   // R rank
+    if (b != a && y != x) {
+        const uint32_t lb = f.off_l[b], db = f.off_l[b + 1] - lb;
+        const uint32_t ly = f.off_r[y], dy = f.off_r[y + 1] - ly;
+        if (db <= dy) {
+            t.row = f.adj_l + lb;
+            t.hi = db;
+            t.target = y;
+        } else {
+            t.row = f.adj_r + ly;
+            t.hi = dy;
+            t.target = b;
+        }
+    }
+    return t;
+}
+
+// One wave per unit (draw, 64 consecutive trials), one trial per lane; a
+// wave adds its hits to the draw's counter with one atomic.  Every probe
+// index lies in [lo, hi), inside the probed row.  Running two or four units
+// side by side per wave was slower: a wave's searches diverge, and the
+// merged loop runs as long as the longest of them.
 __global__ __launch_bounds__(256) void k_fast_trials(FastArgs f, uint32_t *hits) {
     const uint32_t lane = threadIdx.x & (WAVE - 1);
     const uint64_t nchunk = (f.alpha + WAVE - 1) / WAVE;
@@ -427,29 +473,18 @@ __global__ __launch_bounds__(256) void k_fast_trials(FastArgs f, uint32_t *hits)
          u += nwaves) {
         const uint64_t i = u / nchunk;
         const uint32_t j = (uint32_t)(u - i * nchunk) * WAVE + lane;
-        bool hit = false;
-        if (j < f.alpha) {
-            const uint32_t a = f.ea[i], x = f.ex[i];
-            const uint32_t la = f.off_l[a], da = f.off_l[a + 1] - la;
-            const uint32_t lx = f.off_r[x], dx = f.off_r[x + 1] - lx;
-            const uint64_t rx = (0 - (uint64_t)dx) % dx, ra = (0 - (uint64_t)da) % da;
-            uint32_t o[4];
-            uint64_t x1, x2;
-            for (uint32_t attempt = 0;; attempt++) {
-                philox((uint32_t)i, j, TAG_FAST, attempt, f.seed, o);
-                x1 = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
-                x2 = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
-                if ((rx == 0 || x1 < 0 - rx) && (ra == 0 || x2 < 0 - ra)) break;
-            }
-            const uint32_t b = f.adj_r[lx + (uint32_t)(x1 % dx)];   // L rank
-            const uint32_t y = f.adj_l[la + (uint32_t)(x2 % da)];   // R rank
-            if (b != a && y != x) {
-                const uint32_t lb = f.off_l[b], db = f.off_l[b + 1] - lb;
-                const uint32_t ly = f.off_r[y], dy = f.off_r[y + 1] - ly;
-                hit = db <= dy ? in_sorted(f.adj_l + lb, db, y) : in_sorted(f.adj_r + ly, dy, b);
+        Probe t = trial_probe(f, i, j, j < f.alpha);
+        while (t.lo < t.hi) {
+            const uint32_t mid = (t.lo + t.hi) >> 1;
+            const uint32_t v = t.row[mid];
+            if (v < t.target) {
+                t.lo = mid + 1;
+            } else {
+                t.hi = mid;
+                t.found |= v == t.target;
             }
         }
-        const uint64_t mask = __ballot(hit);
+        const uint64_t mask = __ballot(t.found);
         if (lane == 0 && mask) atomicAdd(&hits[i], (uint32_t)__popcll(mask));
     }
 }
