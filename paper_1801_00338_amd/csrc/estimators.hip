@@ -554,6 +554,35 @@ __global__ void k_wedge_weights(uint32_t nl, uint32_t nr, const uint32_t *rank_l
     }
 }
 
+// First index v < n with pre[v] > t (n if none), pre non-decreasing, found
+// by the whole wave: each step the 64 lanes read 64 evenly spaced entries
+// of the remaining range and a ballot keeps the segment holding the
+// answer, so about log64(n) dependent reads instead of log2(n).  Every lane
+// returns the same index.
+__device__ inline uint64_t wave_first_above(const unsigned long long *pre, uint64_t n, uint64_t t,
+                                            uint32_t lane) {
+    uint64_t lo = 0, hi = n;            // answer in [lo, hi]; hi == n or pre[hi] > t
+    while (hi - lo > WAVE) {
+        const uint64_t step = (hi - lo + WAVE - 1) / WAVE;
+        const uint64_t e = lo + (uint64_t)(lane + 1) * step;
+        const uint64_t p = (e < hi ? e : hi) - 1;   // probe of this lane, in [lo, hi)
+        const uint64_t mask = __ballot(pre[p] > t);
+        if (!mask) {
+            lo = hi;                    // every probe, the last one included, is <= t
+        } else {
+            const uint32_t f = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+            const uint64_t ef = lo + (uint64_t)(f + 1) * step;
+            const uint64_t pf = (ef < hi ? ef : hi) - 1;
+            const uint64_t nlo = f ? lo + (uint64_t)f * step : lo;   // one past probe f - 1
+            lo = nlo < pf ? nlo : pf;
+            hi = pf;
+        }
+    }
+    const uint64_t q = lo + lane;
+    const uint64_t mask = __ballot(q < hi && pre[q] > t);
+    return mask ? lo + (uint64_t)__ffsll((unsigned long long)mask) - 1 : hi;
+}
+
 struct WsampArgs {
     const uint32_t *off_l, *adj_l, *off_r, *adj_r, *rank_l, *rank_r, *id_l, *id_r;
     const unsigned long long *pre;      // inclusive prefix sums of C(d,2), global order
@@ -571,12 +600,7 @@ __global__ __launch_bounds__(256) void k_wsamp(WsampArgs a, uint32_t *mids, uint
     for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE; i < a.k;
          i += nwaves) {
         const uint64_t t = draw_below(a.seed, (uint32_t)i, (uint32_t)(i >> 32), TAG_WDRAW, a.W);
-        uint64_t lo = 0, hi = a.n;            // midpoint: first v with pre[v] > t
-        while (lo < hi) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            if (a.pre[mid] > t) hi = mid; else lo = mid + 1;
-        }
-        const uint64_t u = lo;
+        const uint64_t u = wave_first_above(a.pre, a.n, t, lane);
         if (u >= a.n) {                       // totals disagree: report nothing, read nothing
             if (lane == 0) {
                 mids[i] = 0xFFFFFFFFu;
@@ -617,7 +641,21 @@ __global__ __launch_bounds__(256) void k_wsamp(WsampArgs a, uint32_t *mids, uint
         uint64_t c = 0;
         for (uint32_t b0 = 0; b0 < ds; b0 += WAVE) {
             const uint32_t idx = b0 + lane;
-            const bool found = idx < ds && in_sorted(adjB + lb, db, adjB[ls + idx]);
+            bool found = false;
+            if (idx < ds) {
+                const uint32_t target = adjB[ls + idx], *row = adjB + lb;
+                uint32_t lo = 0, hi = db;     // lower bound, found when probed equal
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    const uint32_t v = row[mid];
+                    if (v < target) {
+                        lo = mid + 1;
+                    } else {
+                        hi = mid;
+                        found |= v == target;
+                    }
+                }
+            }
             c += (uint64_t)__popcll(__ballot(found));
         }
         if (lane == 0) {
