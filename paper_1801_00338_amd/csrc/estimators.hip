@@ -407,15 +407,6 @@ __global__ void k_fast_setup(uint64_t k, const unsigned long long *draw, const u
     }
 }
 
-__device__ inline bool in_sorted(const uint32_t *a, uint32_t n, uint32_t t) {
-    uint32_t lo = 0, hi = n;                  // first position with a[pos] >= t
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] < t) lo = mid + 1; else hi = mid;
-    }
-    return lo < n && a[lo] == t;
-}
-
 // One trial's probe: lower bound of `target` in row[lo..hi), with `found`
 // set when a probe equals it (the lower bound is always probed before the
 // search ends, so no final load is needed).  Lanes without a probe (a miss
