@@ -412,15 +412,31 @@ def bench_esamp_fast(args):
         log(f"alpha={alpha}: sigma1={math.sqrt(v1):.4g} k={k} query {t * 1e3:.2f} ms")
         cands.append((t, alpha, k, math.sqrt(v1)))
     t, alpha, k, sig = min(cands)
+
+    def p95_of(run, budget_s):
+        errs, t0 = [], time.perf_counter()
+        for s in range(args.trials):
+            if time.perf_counter() - t0 > budget_s:
+                break
+            errs.append(abs(run((5 << 40) | s) - B) / B)
+        return float(np.percentile(errs, 95)), len(errs)
+
+    def fast_run(bufs, seed):
+        g.esamp_fast_async(bufs, alpha, seed)
+        return float(bufs["est"].item())
+
     bufs = g.esamp_fast_buffers(k)
-    errs, t0 = [], time.perf_counter()
-    for s in range(args.trials):
-        if time.perf_counter() - t0 > 60.0:
-            break
-        g.esamp_fast_async(bufs, alpha, (5 << 40) | s)
-        errs.append(abs(float(bufs["est"].item()) - B) / B)
-    p95 = float(np.percentile(errs, 95))
-    log(f"best alpha={alpha} k={k}: {t * 1e3:.2f} ms; p95 error {p95:.4f} over {len(errs)} seeds")
+    p95, nseeds = p95_of(lambda sd: fast_run(bufs, sd), 60.0)
+    log(f"best alpha={alpha} k={k}: {t * 1e3:.2f} ms; p95 error {p95:.4f} over {nseeds} seeds")
+    k_closed = k
+    if p95 > 0.01:
+        # the closed form assumes a normal tail: grow k by the measured shortfall, once
+        k = int(math.ceil(k * (p95 / 0.01) ** 2 * 1.05))
+        del bufs
+        t, bufs = query_s(k, alpha)
+        p95, nseeds = p95_of(lambda sd: fast_run(bufs, sd), 60.0)
+        log(f"resized k={k}: {t * 1e3:.2f} ms; p95 error {p95:.4f} over {nseeds} seeds")
+    del bufs
     # ESamp with exact per-edge counts (Sec. 5.2) at its own k
     v1e = (m / 4) ** 2 * float(np.mean(ce * ce)) - float(B) ** 2
     ke = k_for(v1e)
@@ -435,25 +451,32 @@ def bench_esamp_fast(args):
     torch.cuda.synchronize(dev)
     sig_w = (Wt / 4) * float(pilot["cnt"].double().std())
     del pilot
-    kw = k_for(sig_w ** 2)
-    bw = g.wsamp_buffers(kw)
-    g.wsamp_async(bw, 4)
-    torch.cuda.synchronize(dev)
-    tw = []
-    for s_ in range(3):
-        t0 = time.perf_counter()
-        g.wsamp_async(bw, 5 + s_)
+    def wsamp_at(kw):
+        bw = g.wsamp_buffers(kw)
+        g.wsamp_async(bw, 4)
         torch.cuda.synchronize(dev)
-        tw.append(time.perf_counter() - t0)
-    errs_w, t0 = [], time.perf_counter()
-    for s_ in range(args.trials):
-        if time.perf_counter() - t0 > 30.0:
-            break
-        g.wsamp_async(bw, (5 << 40) | s_)
-        errs_w.append(abs(float(bw["est"].item()) - B) / B)
-    del bw
-    wsamp = {"k": kw, "s": float(np.median(tw)), "sigma1_pilot": sig_w,
-             "p95_rel_err": float(np.percentile(errs_w, 95)), "seeds": len(errs_w)}
+        tw = []
+        for s_ in range(3):
+            t0 = time.perf_counter()
+            g.wsamp_async(bw, 5 + s_)
+            torch.cuda.synchronize(dev)
+            tw.append(time.perf_counter() - t0)
+
+        def run(seed):
+            g.wsamp_async(bw, seed)
+            return float(bw["est"].item())
+
+        p, n = p95_of(run, 30.0)
+        return float(np.median(tw)), p, n
+
+    kw = k_for(sig_w ** 2)
+    kw_closed = kw
+    tw, p95w, nw = wsamp_at(kw)
+    if p95w > 0.01:
+        kw = int(math.ceil(kw * (p95w / 0.01) ** 2 * 1.05))
+        tw, p95w, nw = wsamp_at(kw)
+    wsamp = {"k": kw, "k_from_pilot": kw_closed, "s": tw, "sigma1_pilot": sig_w,
+             "p95_rel_err": p95w, "seeds": nw}
     log(f"WSamp: {wsamp}")
     # VSamp (Sec. 5.1), uniform: closed-form k from the exact per-vertex counts
     cl, cr = g.per_vertex()
@@ -474,8 +497,8 @@ def bench_esamp_fast(args):
         "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": t * 1e3, "higher_is_better": False,
         "scaling": "strong", "vs_baseline": None, "dtype": "u32 hits, f64 estimate",
         "data": "synthetic",
-        "config": dict(w.describe(), butterflies=B, alpha=alpha, k=k, sigma1=sig,
-                       p95_rel_err=p95, seeds=len(errs),
+        "config": dict(w.describe(), butterflies=B, alpha=alpha, k=k, k_closed_form=k_closed,
+                       sigma1=sig, p95_rel_err=p95, seeds=nseeds,
                        step="edge draws, position map, alpha trials per draw, estimate"),
         "esamp_exact_ebfc": {"k": ke, "s": esamp_s},
         "wsamp": wsamp,
