@@ -41,8 +41,8 @@ def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (plain -O2, no GPU code)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-Wall", "-shared", "-fPIC",
+                               "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -74,6 +74,9 @@ def lib():
         L.orc_fast_ebfc_pairs.argtypes = g + [C.c_uint64, u64p]
         L.orc_wsamp.argtypes = g + [C.c_uint64, C.c_uint64, u32p, u32p, u64p, dp]
         L.orc_wedges.argtypes = g + [u64p, C.c_uint64, u32p, u32p, u64p, u64p]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_philox4x32_10.restype = None
         L.orc_color.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
@@ -82,6 +85,14 @@ def lib():
                                         C.c_uint64, u64p]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads over start vertices for exact, exact_range, per_vertex and
+    per_edge (1 = in order on the calling thread, the default).  Results do
+    not depend on it.  Returns the setting in force."""
+    lib().orc_set_threads(int(n))
+    return int(lib().orc_get_threads())
 
 
 def _edges(l, r):

@@ -32,6 +32,7 @@
  * edges), Philox known-answer vectors, estimator special cases (p = 1, N = 1,
  * proposal proportional to the local count).  The tests hold them.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -145,6 +146,64 @@ static int graph_build(graph_t *g, uint32_t nl, uint32_t nr, uint64_t m,
 static inline uint64_t choose2(uint64_t c) { return c < 2 ? 0 : c * (c - 1) / 2; }
 
 /* ------------------------------------------------------------------ */
+/* Threads over start vertices.  The counts of different starts are     */
+/* independent (each start has its own counter array), so the starts of */
+/* a loop may be handed to several threads in chunks; integer sums do   */
+/* not depend on the order in which chunks finish.  One thread (the     */
+/* default) runs the loop in order on the calling thread.               */
+/* ------------------------------------------------------------------ */
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n < 1 ? 1 : (n > 256 ? 256 : n); }
+int orc_get_threads(void) { return g_threads; }
+
+typedef void (*range_fn)(void *ctx, int worker, uint64_t lo, uint64_t hi);
+
+typedef struct {
+    range_fn fn;
+    void *ctx;
+    uint64_t next, end, chunk;
+    int worker;
+} pool_t;
+
+static void *pool_main(void *arg) {
+    pool_t *p = ((pool_t **)arg)[0];
+    int worker = (int)(intptr_t)((void **)arg)[1];
+    for (;;) {
+        uint64_t lo = __atomic_fetch_add(&p->next, p->chunk, __ATOMIC_RELAXED);
+        if (lo >= p->end) break;
+        uint64_t hi = lo + p->chunk < p->end ? lo + p->chunk : p->end;
+        p->fn(p->ctx, worker, lo, hi);
+    }
+    return NULL;
+}
+
+/* Run fn over [lo, hi) in chunks on `workers` threads (worker ids 0 ..
+ * workers-1 index per-thread scratch).  Returns the number of workers used. */
+static int parallel_range(range_fn fn, void *ctx, uint64_t lo, uint64_t hi, int workers,
+                          uint64_t chunk) {
+    if (workers <= 1 || hi - lo <= chunk) {
+        if (lo < hi) fn(ctx, 0, lo, hi);
+        return 1;
+    }
+    pool_t p = {fn, ctx, lo, hi, chunk, 0};
+    pthread_t th[256];
+    void *args[256][2];
+    int started = 0;
+    for (int t = 1; t < workers; t++) {
+        args[t][0] = &p;
+        args[t][1] = (void *)(intptr_t)t;
+        if (pthread_create(&th[t], NULL, pool_main, args[t]) != 0) break;
+        started = t;
+    }
+    args[0][0] = &p;
+    args[0][1] = (void *)(intptr_t)0;
+    pool_main(args[0]);
+    for (int t = 1; t <= started; t++) pthread_join(th[t], NULL);
+    return started + 1;
+}
+
+/* ------------------------------------------------------------------ */
 /* Exact count: ExactBFC (Sec. 4).                                      */
 /*                                                                      */
 /* Side choice: start from L unless sum_{L} d^2 < sum_{R} d^2, in which */
@@ -156,23 +215,41 @@ static inline uint64_t choose2(uint64_t c) { return c < 2 ? 0 : c * (c - 1) / 2;
 /* `side`: 0 = the paper's rule, 1 = start from L, 2 = start from R.    */
 /* `wedges` receives the number of (v,u,w) triples visited.            */
 /* ------------------------------------------------------------------ */
-static int exact_on(const graph_t *g, int side, uint64_t start_lo, uint64_t start_hi,
-                    uint64_t *total, uint64_t *wedges, int *side_used) {
-    uint64_t sl = 0, sr = 0;
-    for (uint32_t v = 0; v < g->L.n; v++) { uint64_t d = g->L.off[v + 1] - g->L.off[v]; sl += d * d; }
-    for (uint32_t v = 0; v < g->R.n; v++) { uint64_t d = g->R.off[v + 1] - g->R.off[v]; sr += d * d; }
-    int start_r;
-    if (side == 1) start_r = 0;
-    else if (side == 2) start_r = 1;
-    else start_r = (sl < sr);
-    const adj_t *A = start_r ? &g->R : &g->L;   /* starts and end points */
-    const adj_t *B = start_r ? &g->L : &g->R;   /* midpoints */
-    uint32_t *C = (uint32_t *)calloc((size_t)A->n + 1, sizeof(uint32_t));
-    uint32_t *touched = (uint32_t *)malloc(((size_t)A->n + 1) * sizeof(uint32_t));
-    if (!C || !touched) { free(C); free(touched); return ORC_E_NOMEM; }
+/* Per-thread counter arrays of one loop over starts (zeroed, n + 1 each). */
+typedef struct {
+    int workers;
+    uint32_t *C[256], *T[256];
+    uint64_t sum[256], visits[256];
+} scratch_t;
+
+static void scratch_free(scratch_t *s) {
+    for (int t = 0; t < s->workers; t++) { free(s->C[t]); free(s->T[t]); }
+    memset(s, 0, sizeof(*s));
+}
+
+static int scratch_init(scratch_t *s, uint64_t n) {
+    memset(s, 0, sizeof(*s));
+    s->workers = g_threads;
+    for (int t = 0; t < s->workers; t++) {
+        s->C[t] = (uint32_t *)calloc((size_t)n + 1, sizeof(uint32_t));
+        s->T[t] = (uint32_t *)malloc(((size_t)n + 1) * sizeof(uint32_t));
+        if (!s->C[t] || !s->T[t]) { scratch_free(s); return ORC_E_NOMEM; }
+    }
+    return ORC_OK;
+}
+
+typedef struct {
+    const adj_t *A, *B;
+    scratch_t *sc;
+} exact_ctx;
+
+/* ExactBFC's loop body for the starts v in [lo, hi). */
+static void exact_starts(void *vctx, int worker, uint64_t lo, uint64_t hi) {
+    exact_ctx *x = (exact_ctx *)vctx;
+    const adj_t *A = x->A, *B = x->B;
+    uint32_t *C = x->sc->C[worker], *touched = x->sc->T[worker];
     uint64_t sum = 0, visits = 0;
-    if (start_hi > A->n) start_hi = A->n;
-    for (uint64_t v = start_lo; v < start_hi; v++) {
+    for (uint64_t v = lo; v < hi; v++) {
         uint32_t nt = 0;
         for (uint64_t k = A->off[v]; k < A->off[v + 1]; k++) {
             uint32_t u = A->nbr[k];
@@ -189,7 +266,30 @@ static int exact_on(const graph_t *g, int side, uint64_t start_lo, uint64_t star
             C[touched[t]] = 0;
         }
     }
-    free(C); free(touched);
+    x->sc->sum[worker] += sum;
+    x->sc->visits[worker] += visits;
+}
+
+static int exact_on(const graph_t *g, int side, uint64_t start_lo, uint64_t start_hi,
+                    uint64_t *total, uint64_t *wedges, int *side_used) {
+    uint64_t sl = 0, sr = 0;
+    for (uint32_t v = 0; v < g->L.n; v++) { uint64_t d = g->L.off[v + 1] - g->L.off[v]; sl += d * d; }
+    for (uint32_t v = 0; v < g->R.n; v++) { uint64_t d = g->R.off[v + 1] - g->R.off[v]; sr += d * d; }
+    int start_r;
+    if (side == 1) start_r = 0;
+    else if (side == 2) start_r = 1;
+    else start_r = (sl < sr);
+    exact_ctx x;
+    x.A = start_r ? &g->R : &g->L;   /* starts and end points */
+    x.B = start_r ? &g->L : &g->R;   /* midpoints */
+    scratch_t sc;
+    if (scratch_init(&sc, x.A->n)) return ORC_E_NOMEM;
+    x.sc = &sc;
+    if (start_hi > x.A->n) start_hi = x.A->n;
+    if (start_lo < start_hi) parallel_range(exact_starts, &x, start_lo, start_hi, sc.workers, 256);
+    uint64_t sum = 0, visits = 0;
+    for (int t = 0; t < sc.workers; t++) { sum += sc.sum[t]; visits += sc.visits[t]; }
+    scratch_free(&sc);
     *total = sum;
     if (wedges) *wedges = visits;
     if (side_used) *side_used = start_r ? 2 : 1;
@@ -263,6 +363,18 @@ static void vbfc_side(const adj_t *A, const adj_t *B, uint32_t v, uint32_t *C,
     *out = s;
 }
 
+typedef struct {
+    const adj_t *A, *B;
+    scratch_t *sc;
+    uint64_t *out;
+} vbfc_ctx;
+
+static void vbfc_range(void *vctx, int worker, uint64_t lo, uint64_t hi) {
+    vbfc_ctx *x = (vbfc_ctx *)vctx;
+    for (uint64_t v = lo; v < hi; v++)
+        vbfc_side(x->A, x->B, (uint32_t)v, x->sc->C[worker], x->sc->T[worker], &x->out[v]);
+}
+
 int orc_per_vertex(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l, const uint32_t *r,
                    uint64_t *cnt_l, uint64_t *cnt_r) {
     if ((nl && !cnt_l) || (nr && !cnt_r)) return ORC_E_ARG;
@@ -270,11 +382,12 @@ int orc_per_vertex(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l, cons
     int rc = graph_build(&g, nl, nr, m, l, r);
     if (rc) return rc;
     uint32_t n = nl > nr ? nl : nr;
-    uint32_t *C = (uint32_t *)calloc((size_t)n + 1, 4), *T = (uint32_t *)malloc(((size_t)n + 1) * 4);
-    if (!C || !T) { free(C); free(T); graph_free(&g); return ORC_E_NOMEM; }
-    for (uint32_t v = 0; v < nl; v++) vbfc_side(&g.L, &g.R, v, C, T, &cnt_l[v]);
-    for (uint32_t v = 0; v < nr; v++) vbfc_side(&g.R, &g.L, v, C, T, &cnt_r[v]);
-    free(C); free(T); graph_free(&g);
+    scratch_t sc;
+    if (scratch_init(&sc, n)) { graph_free(&g); return ORC_E_NOMEM; }
+    vbfc_ctx xl = {&g.L, &g.R, &sc, cnt_l}, xr = {&g.R, &g.L, &sc, cnt_r};
+    parallel_range(vbfc_range, &xl, 0, nl, sc.workers, 256);
+    parallel_range(vbfc_range, &xr, 0, nr, sc.workers, 256);
+    scratch_free(&sc); graph_free(&g);
     return ORC_OK;
 }
 
@@ -306,38 +419,53 @@ int orc_vbfc(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l, const uint
 /* edge (a, x) of a is folded from them, which is eBFC for all edges of */
 /* a at once.                                                           */
 /* ------------------------------------------------------------------ */
+typedef struct {
+    const graph_t *g;
+    scratch_t *sc;
+    uint64_t *cnt_e;
+} edge_ctx;
+
+/* The edges of the L vertices a in [lo, hi). */
+static void edge_range(void *vctx, int worker, uint64_t lo, uint64_t hi) {
+    edge_ctx *x = (edge_ctx *)vctx;
+    const graph_t *g = x->g;
+    uint32_t *C = x->sc->C[worker], *T = x->sc->T[worker];
+    for (uint64_t a = lo; a < hi; a++) {
+        uint32_t nt = 0;
+        for (uint64_t k = g->L.off[a]; k < g->L.off[a + 1]; k++) {
+            uint32_t u = g->L.nbr[k];
+            for (uint64_t j = g->R.off[u]; j < g->R.off[u + 1]; j++) {
+                uint32_t b = g->R.nbr[j];
+                if (b == a) continue;
+                if (C[b] == 0) T[nt++] = b;
+                C[b]++;
+            }
+        }
+        for (uint64_t k = g->L.off[a]; k < g->L.off[a + 1]; k++) {
+            uint32_t x2 = g->L.nbr[k];
+            uint64_t s = 0;
+            for (uint64_t j = g->R.off[x2]; j < g->R.off[x2 + 1]; j++) {
+                uint32_t b = g->R.nbr[j];
+                if (b == a) continue;
+                s += (uint64_t)C[b] - 1;   /* C[b] >= 1: x2 is common */
+            }
+            x->cnt_e[g->L.eid[k]] = s;
+        }
+        for (uint32_t t = 0; t < nt; t++) C[T[t]] = 0;
+    }
+}
+
 int orc_per_edge(uint32_t nl, uint32_t nr, uint64_t m, const uint32_t *l, const uint32_t *r,
                  uint64_t *cnt_e) {
     if (m && !cnt_e) return ORC_E_ARG;
     graph_t g;
     int rc = graph_build(&g, nl, nr, m, l, r);
     if (rc) return rc;
-    uint32_t *C = (uint32_t *)calloc((size_t)nl + 1, 4), *T = (uint32_t *)malloc(((size_t)nl + 1) * 4);
-    if (!C || !T) { free(C); free(T); graph_free(&g); return ORC_E_NOMEM; }
-    for (uint32_t a = 0; a < nl; a++) {
-        uint32_t nt = 0;
-        for (uint64_t k = g.L.off[a]; k < g.L.off[a + 1]; k++) {
-            uint32_t u = g.L.nbr[k];
-            for (uint64_t j = g.R.off[u]; j < g.R.off[u + 1]; j++) {
-                uint32_t b = g.R.nbr[j];
-                if (b == a) continue;
-                if (C[b] == 0) T[nt++] = b;
-                C[b]++;
-            }
-        }
-        for (uint64_t k = g.L.off[a]; k < g.L.off[a + 1]; k++) {
-            uint32_t x = g.L.nbr[k];
-            uint64_t s = 0;
-            for (uint64_t j = g.R.off[x]; j < g.R.off[x + 1]; j++) {
-                uint32_t b = g.R.nbr[j];
-                if (b == a) continue;
-                s += (uint64_t)C[b] - 1;   /* C[b] >= 1: x is common */
-            }
-            cnt_e[g.L.eid[k]] = s;
-        }
-        for (uint32_t t = 0; t < nt; t++) C[T[t]] = 0;
-    }
-    free(C); free(T); graph_free(&g);
+    scratch_t sc;
+    if (scratch_init(&sc, nl)) { graph_free(&g); return ORC_E_NOMEM; }
+    edge_ctx x = {&g, &sc, cnt_e};
+    parallel_range(edge_range, &x, 0, nl, sc.workers, 256);
+    scratch_free(&sc); graph_free(&g);
     return ORC_OK;
 }
 

@@ -174,6 +174,64 @@ def test_invariants_random():
         assert W == int((d * (d - 1) // 2).sum())
 
 
+def test_exact_range_per_start_vs_brute():
+    """orc_exact_range: the partial sums of Eq. (3)/(4) over a start range.
+
+    For one start v of the start side, the range [v, v + 1) must give
+    sum_{w < v} C(|N(v) & N(w)|, 2) (set intersections written out here) and
+    visit sum_{u in N(v)} #{w in N(u): w < v} wedges; disjoint ranges add up
+    to the full count, and the full range is orc_exact.
+    """
+    from math import comb
+    rng = np.random.default_rng(8)
+    for _ in range(12):
+        nl, nr = (int(x) for x in rng.integers(2, 25, size=2))
+        l, r = rand_graph(rng, nl, nr, rng.integers(0, nl * nr // 2 + 2))
+        B, W, _ = oracle.exact(nl, nr, l, r)
+        for side in (1, 2):
+            A, Bs, nA = (l, r, nl) if side == 1 else (r, l, nr)
+            N = [set() for _ in range(nA)]
+            M = {}
+            for a, b in zip(A.tolist(), Bs.tolist()):
+                N[a].add(b)
+                M.setdefault(b, set()).add(a)
+            tot = wed = 0
+            for v in range(nA):
+                want = sum(comb(len(N[v] & N[w]), 2) for w in range(v))
+                want_w = sum(sum(1 for w in M[u] if w < v) for u in N[v])
+                got, gw, su = oracle.exact_range(nl, nr, l, r, side, v, v + 1)
+                assert (got, gw, su) == (want, want_w, side)
+                tot += got
+                wed += gw
+            assert tot == B
+            cut = sorted(rng.integers(0, nA + 1, size=2).tolist())
+            parts = [oracle.exact_range(nl, nr, l, r, side, a, b)
+                     for a, b in ((0, cut[0]), (cut[0], cut[1]), (cut[1], nA))]
+            assert sum(p[0] for p in parts) == B
+            assert sum(p[1] for p in parts) == oracle.exact(nl, nr, l, r, side)[1]
+            assert oracle.exact_range(nl, nr, l, r, side, 0, nA)[:2] == \
+                oracle.exact(nl, nr, l, r, side)[:2]
+            # an empty or out-of-range slice counts nothing
+            assert oracle.exact_range(nl, nr, l, r, side, nA, nA + 5)[:2] == (0, 0)
+
+
+def test_threads_do_not_change_results():
+    """Threads over starts only split the start loop: identical integers."""
+    nl, nr = 3_000, 15_000
+    l, r = gen.chung_lu(nl, nr, 150_000, 2.1, 2.3, 2000, seed=7)
+    try:
+        one = (oracle.exact(nl, nr, l, r), oracle.exact_range(nl, nr, l, r, 0, 100, 2_500),
+               oracle.per_vertex(nl, nr, l, r), oracle.per_edge(nl, nr, l, r))
+        assert oracle.set_threads(4) == 4
+        many = (oracle.exact(nl, nr, l, r), oracle.exact_range(nl, nr, l, r, 0, 100, 2_500),
+                oracle.per_vertex(nl, nr, l, r), oracle.per_edge(nl, nr, l, r))
+    finally:
+        oracle.set_threads(1)
+    assert one[0] == many[0] and one[1] == many[1]
+    assert np.array_equal(one[2][0], many[2][0]) and np.array_equal(one[2][1], many[2][1])
+    assert np.array_equal(one[3], many[3])
+
+
 def test_local_counts_vs_brute():
     rng = np.random.default_rng(4)
     for _ in range(40):
