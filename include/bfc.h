@@ -401,7 +401,10 @@ int bfc_adam_step(float *d_params, float *d_m1, float *d_m2, const float *d_grad
                   uint32_t step, hipStream_t stream);
 /* Probabilities for bfc_vsamp from predictions y (n floats, predicting
  * log1p(B_v)/8): p_v = max(expm1(8 y_v), floor_frac * mean_v expm1(8 y_v)^+),
- * the mean reduced in a fixed order; *d_mean (may be NULL) gets the mean. */
+ * the mean reduced in a fixed order; *d_mean (may be NULL) gets the mean.
+ * floor_frac must be positive and finite (else BFC_E_ARG), so every p_v > 0
+ * and the weighted VSamp estimate is unbiased for any predictions; when no
+ * prediction is positive (mean 0) every p_v = 1 (uniform sampling). */
 int bfc_probs_ws_size(size_t *bytes);
 int bfc_probs_from_predictions(const float *d_y, uint64_t n, double floor_frac, double *d_probs,
                                double *d_mean, void *d_ws, size_t ws_bytes, hipStream_t stream);

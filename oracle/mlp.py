@@ -199,9 +199,18 @@ def adam(params, m1, m2, g, lr, beta1, beta2, eps, step):
 
 # ------------------------------------------------------------------ sampling side
 def probs_from_predictions(y, floor_frac):
-    """q_v = max(expm1(8 y_v), floor_frac * mean_v max(expm1(8 y_v), 0))."""
+    """q_v = max(expm1(8 y_v), floor_frac * mean_v max(expm1(8 y_v), 0)).
+
+    floor_frac > 0 keeps every q_v positive, so the Hansen-Hurwitz estimate
+    is unbiased whatever the network predicts; with no positive prediction
+    (mean 0) the floor is empty and uniform sampling (q_v = 1) is used.
+    """
+    if not floor_frac > 0:
+        raise ValueError("floor_frac must be positive")
     v = np.expm1(8.0 * np.asarray(y, np.float64))
     mean = np.maximum(v, 0.0).sum() / len(v)
+    if mean == 0:
+        return np.ones_like(v), mean
     return np.maximum(v, floor_frac * mean), mean
 
 

@@ -442,9 +442,12 @@ __global__ void k_targets(const uint64_t *cnt, uint64_t n, float *t) {
 }
 
 // Sampling probabilities from predictions of log1p(B_v)/8: q_v =
-// max(expm1(8 y_v), floor * mean) with mean the mean predicted count.  The
-// mean is reduced in a fixed order (per-block partials, then the partials in
-// block order), so the probabilities are reproducible.
+// max(expm1(8 y_v), floor * mean) with mean the mean of the positive
+// predicted counts and floor > 0, so every q_v > 0 (the Hansen-Hurwitz
+// estimate stays unbiased whatever the network predicts); when no prediction
+// is positive (mean 0) every q_v = 1, plain uniform sampling.  The mean is
+// reduced in a fixed order (per-block partials, then the partials in block
+// order), so the probabilities are reproducible.
 constexpr int PROB_BLOCKS = 1024;
 
 __global__ __launch_bounds__(256) void k_pred_partial(const float *y, uint64_t n, double *part) {
@@ -482,7 +485,7 @@ __global__ __launch_bounds__(256) void k_pred_probs(const float *y, uint64_t n, 
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const double v = expm1(8.0 * (double)y[i]);
-        probs[i] = v > fl ? v : fl;
+        probs[i] = mean_s > 0.0 ? (v > fl ? v : fl) : 1.0;
     }
 }
 
@@ -598,7 +601,7 @@ int bfc_probs_ws_size(size_t *bytes) {
 int bfc_probs_from_predictions(const float *d_y, uint64_t n, double floor_frac, double *d_probs,
                                double *d_mean, void *d_ws, size_t ws_bytes, hipStream_t s) {
     if (!d_y || !d_probs || !d_ws) return BFC_E_NULL;
-    if (n == 0 || !(floor_frac >= 0.0)) return BFC_E_ARG;
+    if (n == 0 || !(floor_frac > 0.0) || !(floor_frac <= 1e300)) return BFC_E_ARG;
     if (ws_bytes < PROB_BLOCKS * sizeof(double)) return BFC_E_WS_SMALL;
     double *part = (double *)d_ws;
     k_pred_partial<<<PROB_BLOCKS, 256, 0, s>>>(d_y, n, part);
