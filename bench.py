@@ -50,28 +50,63 @@ def traffic_from_profiles(workload, kernel):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, l, r, side, target_s):
-    """The CPU oracle timed on this host on a bounded slice of start vertices."""
+def host_cpu():
+    """CPU model and the cores this process may use (the GPU machine's host share)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail, os.cpu_count() or 1
+
+
+def _time_oracle_slice(w, l, r, side, target_s, threads):
+    """ExactBFC of the oracle over the highest-id starts (the busiest ones in
+    its id order), grown until the counting takes about target_s."""
     import oracle
-    oracle.build(force=False)
+    oracle.set_threads(threads)
     nA = w.nl if side == 1 else w.nr
     t0 = time.perf_counter()
     oracle.exact_range(w.nl, w.nr, l, r, side, 0, 0)
     t_build = time.perf_counter() - t0
-    k = 2000
+    k = 2000 * threads
     while True:
+        k = min(k, nA)
         t0 = time.perf_counter()
         _, wed, _ = oracle.exact_range(w.nl, w.nr, l, r, side, nA - k, nA)
         dt = time.perf_counter() - t0
         count_s = max(dt - t_build, 1e-9)
         if count_s >= target_s or k >= nA:
             break
-        k = min(nA, int(k * max(2.0, 1.5 * target_s / count_s)))
+        k = int(k * max(2.0, 1.5 * target_s / count_s))
+    oracle.set_threads(1)
+    return wed / count_s, (f"ExactBFC over the {k} highest-id starts of side "
+                           f"{'L' if side == 1 else 'R'} ({wed} wedges, {count_s:.1f} s counting "
+                           f"after a {t_build:.1f} s adjacency build), {threads} thread(s)")
+
+
+def cpu_baseline(w, l, r, side, target_s):
+    """The CPU oracle timed on this host on a bounded slice of start vertices:
+    threads over starts on every core this process may use (at most 16, the
+    host share of one GPU), and one thread for reference."""
+    import oracle
+    oracle.build(force=False)
+    model, avail, nproc = host_cpu()
+    threads = max(1, min(16, avail))
+    v_all, s_all = _time_oracle_slice(w, l, r, side, target_s, threads)
+    v_one, s_one = _time_oracle_slice(w, l, r, side, target_s / 2, 1)
     return {
-        "value": wed / count_s, "unit": "wedges/s", "cores": 1, "kind": "oracle",
-        "sample": (f"ExactBFC over the {k} highest-id starts of side {'L' if side == 1 else 'R'} "
-                   f"({wed} wedges, {count_s:.1f} s counting after a {t_build:.1f} s adjacency "
-                   f"build), single thread"),
+        "value": v_all, "unit": "wedges/s", "cores": threads, "kind": "oracle",
+        "sample": s_all, "cpu_model": model, "nproc": nproc, "cores_available": avail,
+        "one_thread": {"value": v_one, "sample": s_one},
     }
 
 
@@ -689,10 +724,15 @@ def main():
     alg_bytes = 4 * W + 12 * w.m + 4 * (nA + 1)
     achieved = alg_bytes / (exact_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(w.name, "k_exact")
-    # local counts: every end point w != u twice (the walk, then the final
-    # counts read back): 16 W; per (start, midpoint) pair 12 B in each pass
-    # and an 8 B per-edge result: 32 m; 8 B per vertex result; offsets.
-    alg_local = 16 * W + 32 * w.m + 8 * (w.nl + w.nr) + 4 * (nA + 1)
+    # local counts, algorithmic bytes: the exact walk's bytes (4 W + 12 m +
+    # 8 n offsets), a second pass over the same wedges to scatter the pair
+    # terms (4 W) and the uint64 results of every vertex and edge (8 (n + m)),
+    # n = |L| + |R|.  This design walks every end point w != u instead of the
+    # filtered ones, and reads the final counts back, so it moves about twice
+    # that (design_bytes).
+    n_all = w.nl + w.nr
+    alg_local = 8 * W + 12 * w.m + 8 * n_all + 8 * (n_all + w.m)
+    design_local = 16 * W + 32 * w.m + 8 * n_all + 4 * (nA + 1)
     achieved_local = alg_local / (local_ms * 1e-3) / 1e9
     line = {
         "metric": "wedges/s + HBM GB/s (exact); GPU time to 1% rel. err, learned vs uniform vsamp",
@@ -721,7 +761,8 @@ def main():
                            "unit": "GB/s", "frac": achieved_local / HBM_PEAK_GBS,
                            "traffic": traffic_from_profiles(w.name, "k_local"),
                            "kernel": "k_local_narrow + k_local_wide (+ plan and finish)",
-                           "alg_bytes_per_launch": alg_local},
+                           "alg_bytes_per_launch": alg_local,
+                           "design_bytes_per_launch": design_local},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
