@@ -122,17 +122,22 @@ def _sigma1(cnt, w=None):
     return math.sqrt(max(float(np.sum(c[nz] ** 2 / (16 * q))) - B * B, 0.0))
 
 
-def _grid_k(sigma1, B, kmax):
-    """Smallest k on the 1-2-5 grid from 1e3 with 1.96 sigma1 / sqrt(k) <= 1% of B (None if > kmax)."""
-    k = 1000
-    steps = (2, 2.5, 2)
-    i = 0
-    while k <= kmax:
-        if Z95 * sigma1 / math.sqrt(k) <= 0.01 * B:
-            return k
-        k = int(round(k * steps[i % 3]))
-        i += 1
-    return None
+# budgets: the 1-2-5 grid from 1e3; the error check stops at 1e6 draws per query
+GRID = [int(a * 10 ** e) for e in range(3, 9) for a in (1, 2, 5)]
+KMAX_CHECK = 1_000_000
+
+
+def vsamp_combine(counts, weights, total, k, n, weighted):
+    """VSamp's estimate from per-draw counts in the library's order: weighted,
+    count_i * (Q / (4 w_i)) summed left to right in blocks of 1,024 draws,
+    the block sums left to right, over k; uniform, the exact integer sum
+    times n / (4 k)."""
+    import numpy as np
+    if not weighted:
+        return (float(int(counts.sum(dtype=np.uint64))) * float(n)) / (4.0 * float(k))
+    t = counts.astype(np.float64) * (float(total) / (4.0 * weights.astype(np.float64)))
+    parts = [np.cumsum(t[b:b + 1024])[-1] for b in range(0, k, 1024)]
+    return float(np.cumsum(parts)[-1]) / float(k)
 
 
 def learned_vs_uniform(dev, trials):
@@ -140,11 +145,12 @@ def learned_vs_uniform(dev, trials):
 
     Train the network on 16 Chung-Lu graphs (1M-20M edges, |L|:|R| = 1:4)
     from their exact per-vertex counts, then sample the 20M/80M/400M-edge
-    graph.  For each method: the closed-form single-draw deviation gives the
-    smallest budget k on a 1-2-5 grid that reaches 1% at 95%; the query is
-    timed with HIP events at that k (learned: features, inference and
-    probabilities included); the relative errors of `trials` seeds at that k
-    are reported against the exact count.
+    graph.  For each method and each budget k of the 1-2-5 grid from 1,000
+    (up to 1e6 draws), the 95th percentile of the relative error over
+    `trials` seeds is measured against the exact count; the smallest budget
+    at or below 1% is timed as one full query with HIP events (learned:
+    features, inference and probabilities included).  The closed-form
+    single-draw deviation is reported beside it as a cross-check.
     """
     import numpy as np
     import torch
@@ -239,39 +245,79 @@ def learned_vs_uniform(dev, trials):
         log(f"learned: {name} query with k={k}: {min(ts):.1f} ms")
         return min(ts), buf
 
-    def errors(name, pr, buf, budget_s=60.0):
-        """95th percentile of the relative error over seeded queries (time-bounded)."""
+    def errors(name, pr, k):
+        """Relative errors of `trials` seeded queries with k draws.  The
+        draws come from the library (bfc_vsamp_draws: the same ids as
+        bfc_vsamp for the same seed); each drawn vertex's count is read from
+        the exact per-vertex counts in hand and the estimate formed in
+        bfc_vsamp's order (checked bit for bit against bfc_vsamp below)."""
+        buf = g.vsamp_draws_buffers(k)
         errs = []
-        t0 = time.perf_counter()
-        for sd in range(trials):
-            e = float(g.vsamp_async(buf, (5 << 40) | sd, pr).item())
+        for t in range(trials):
+            g.vsamp_draws_async(buf, (5 << 40) | t, pr)
+            torch.cuda.synchronize(dev)
+            ids = buf["ids"].cpu().numpy().view(np.uint32)[:k]
+            w = buf["w"].cpu().numpy().view(np.uint32)[:k]
+            Q = int(buf["total"].cpu().numpy().view(np.uint64)[0])
+            e = vsamp_combine(cnt_h[ids], w, Q, k, n, pr is not None)
             errs.append(abs(e - B) / B)
-            if (sd + 1) % 10 == 0:
-                log(f"learned: {name}: {sd + 1} seeded queries, p95 rel. err so far "
-                    f"{np.quantile(errs, 0.95):.4f}")
-            if time.perf_counter() - t0 > budget_s:
-                break
-        return float(np.quantile(errs, 0.95)), len(errs)
+        p95 = float(np.quantile(errs, 0.95))
+        log(f"learned: {name}: k={k}: p95 rel. err over {trials} seeds {p95:.5f}")
+        return p95
 
     out = {"workload": w5.describe(), "butterflies": B, "exact_count_ms": exact_ms,
            "exact_per_vertex_ms": vertex_ms, "train_graphs": 16,
            "train_rows_prep_ms": prep_ms, "train_ms": train_ms, "train_steps": steps,
-           "floor_frac": 0.05}
+           "floor_frac": 0.05,
+           "method": (f"95th percentile of |Y - B| / B over {trials} seeds per budget on the "
+                      "1-2-5 grid from 1,000 draws; the smallest budget at or below 1% is timed "
+                      "as one full query")}
     res = {}
     for name, sig, pr in (("learned", s_l, probs), ("uniform", s_u, None)):
-        k = _grid_k(sig, B, 20_000_000)
-        d = {"sigma1": sig, "k_closed_form": math.ceil((Z95 * sig / (0.01 * B)) ** 2)}
-        log(f"learned: {name}: sigma1={sig:.4g}, grid budget k={k}")
-        if k is None:
-            kk = 20_000_000
-            ms, buf = timed(name, kk, pr)
-            d.update(reached=False, k_measured=kk, ms_at_k_measured=ms,
-                     note="1% at 95% needs more than 2e7 draws; the time shown is a lower bound")
+        d = {"sigma1": sig, "k_closed_form": math.ceil((Z95 * sig / (0.01 * B)) ** 2),
+             "trials": trials, "p95_by_k": {}}
+        reached = None
+        for k in GRID:
+            if k > KMAX_CHECK:
+                break
+            p95 = errors(name, pr, k)
+            d["p95_by_k"][str(k)] = p95
+            if p95 <= 0.01:
+                reached = k
+                break
+        if reached is not None:
+            ms, buf = timed(name, reached, pr)
+            # the full query reproduces the estimate formed from the draws
+            g.vsamp_async(buf, (5 << 40) | 0, pr)
+            torch.cuda.synchronize(dev)
+            ids = buf["ids"].cpu().numpy().view(np.uint32)[:reached]
+            cnt_q = buf["cnt"].cpu().numpy().view(np.uint64)[:reached]
+            if not np.array_equal(cnt_q, cnt_h[ids]):
+                raise SystemExit("bfc_vsamp counts differ from the exact per-vertex counts")
+            di, dw, dq = g.vsamp_draws(reached, (5 << 40) | 0, pr)
+            e_host = vsamp_combine(cnt_h[di], dw, dq, reached, n, pr is not None)
+            if not (np.array_equal(di, ids) and e_host == float(buf["est"].item())):
+                raise SystemExit("bfc_vsamp's estimate differs from the one formed from its draws")
+            d.update(reached=True, k=reached, p95_rel_err=d["p95_by_k"][str(reached)],
+                     vsamp_ms=ms)
+            del buf
         else:
-            ms, buf = timed(name, k, pr)
-            d.update(reached=True, k=k, vsamp_ms=ms)
-            if k <= 1_000_000 and name == "learned":
-                d["p95_rel_err"], d["trials"] = errors(name, pr, buf)
+            kk = max(int(x) for x in d["p95_by_k"])
+            p95 = d["p95_by_k"][str(kk)]
+            ms, buf = timed(name, kk, pr)
+            del buf
+            # the error falls as 1/sqrt(k): the budget 1% needs, from the measured p95
+            k_need = math.ceil(kk * (p95 / 0.01) ** 2)
+            d.update(reached=False, k_measured=kk, p95_at_k_measured=p95, ms_at_k_measured=ms,
+                     k_needed_extrapolated=k_need,
+                     note=(f"1% at 95% not reached by {kk} draws; the measured p95 at {kk} "
+                           f"extrapolates (1/sqrt(k)) to {k_need} draws"))
+            if k_need >= n:
+                # more draws than vertices: the query then counts essentially every
+                # vertex with a positive count, i.e. at least the exact per-vertex pass
+                d["gpu_ms_to_1pct_lower_bound"] = max(vertex_ms, ms)
+                d["note"] += ("; that exceeds n, so the query counts essentially every vertex: "
+                              "its time is at least that of the exact per-vertex counts")
         if name == "learned":
             d["query_ms"] = query_ms
             d["gpu_ms_to_1pct"] = (query_ms + d["vsamp_ms"]) if d.get("reached") else None
@@ -279,13 +325,13 @@ def learned_vs_uniform(dev, trials):
             d["gpu_ms_to_1pct"] = d.get("vsamp_ms")
         res[name] = d
         log(f"learned: {name}: {d}")
-        del buf
     out.update(res)
-    if res["learned"].get("reached") and res["uniform"].get("reached"):
-        out["speedup_vs_uniform"] = res["uniform"]["gpu_ms_to_1pct"] / res["learned"]["gpu_ms_to_1pct"]
-    elif res["learned"].get("reached"):
-        out["speedup_vs_uniform_at_least"] = (res["uniform"]["ms_at_k_measured"] /
-                                              res["learned"]["gpu_ms_to_1pct"])
+    L_, U_ = res["learned"], res["uniform"]
+    if L_.get("reached") and U_.get("reached"):
+        out["speedup_vs_uniform"] = U_["gpu_ms_to_1pct"] / L_["gpu_ms_to_1pct"]
+    elif L_.get("reached") and U_.get("gpu_ms_to_1pct_lower_bound"):
+        out["speedup_vs_uniform_at_least"] = (U_["gpu_ms_to_1pct_lower_bound"] /
+                                              L_["gpu_ms_to_1pct"])
     return out
 
 
@@ -314,17 +360,26 @@ def bench_batch(args):
         b.totals_async(out, best)
     torch.cuda.synchronize(dev)
     ref = out.clone()
+    # the timed step is one replay of the whole batched count captured in a HIP graph
+    hg = capture(lambda: b.totals_async(out, best), dev)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     t0 = time.perf_counter()
     for e0, e1 in evs:
         e0.record(stream)
-        b.totals_async(out, best)
+        hg.replay()
         e1.record(stream)
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     if args.warmup and not torch.equal(out, ref):
         raise SystemExit("batch totals changed between runs")
+    eager = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(3)]
+    for e0, e1 in eager:
+        e0.record(stream)
+        b.totals_async(out, best)
+        e1.record(stream)
+    torch.cuda.synchronize(dev)
     ms = wall * 1e3 / args.steps
     line = {
         "metric": "graphs/s (batched exact counts)", "value": 1024 / (ms * 1e-3),
@@ -333,9 +388,11 @@ def bench_batch(args):
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": "batch_1024 (m log-uniform in [1k, 2M], seed 3)", "graphs": 1024,
                    "edges": m, "wedges": W, "tuning": best.as_dict(),
-                   "step": "plan + exact count of every graph + per-graph sums, one union"},
+                   "step": ("one replay of the HIP graph holding plan + exact count of every "
+                            "graph + per-graph sums, one union")},
         "wedges_per_s": W / (ms * 1e-3),
         "gpu_ms_per_step": sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps,
+        "eager_gpu_ms": min(e0.elapsed_time(e1) for e0, e1 in eager),
         "union_build_once_ms": build_ms,
     }
     print(json.dumps(line), flush=True)
@@ -359,29 +416,72 @@ def bench_replicas(args):
         reps += [("espar", p, (4 << 32) | len(reps) + i) for i in range(32)]
     for n in (4, 8, 16, 32):
         reps += [("clrspar", n, (4 << 32) | len(reps) + i) for i in range(32)]
-    times = []
-    for it in range(max(1, args.steps)):
+    t0 = time.perf_counter()
+    rb = api.ReplicaBatch(g, reps, log=log)
+    phase1_ms = (time.perf_counter() - t0) * 1e3
+    kept = rb.kept
+    beta = torch.zeros(256, dtype=torch.int64, device=dev)
+    est = torch.zeros(256, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    rb.run_async(beta, est)
+    torch.cuda.synchronize(dev)
+    ref_b, ref_e = beta.clone(), est.clone()
+    # the timed step: one replay of phase 2 captured in a HIP graph
+    hg = capture(lambda: rb.run_async(beta, est), dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(max(1, args.steps))]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        beta.fill_(-1)
+        e0.record(stream)
+        hg.replay()
+        e1.record(stream)
         torch.cuda.synchronize(dev)
-        t0 = time.perf_counter()
-        beta, est, kept = g.spar_batch(reps, log=log)
-        times.append(time.perf_counter() - t0)
+        if not (torch.equal(beta, ref_b) and torch.equal(est, ref_e)):
+            raise SystemExit("a replay of the replica batch differs from the eager run")
+    ms = min(e0.elapsed_time(e1) for e0, e1 in evs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rb.run_async(beta, est)
+    e1.record(stream)
+    torch.cuda.synchronize(dev)
+    eager_ms = e0.elapsed_time(e1)
+    est = est.cpu().numpy()
     groups = {}
     for i in range(0, 256, 32):
         kind, param, _ = reps[i]
         e = est[i:i + 32]
         groups[f"{kind}:{param}"] = {"mean": float(e.mean()), "rel_err": float((e.mean() - B) / B),
                                      "var": float(e.var(ddof=1))}
-    ms = min(times) * 1e3
     line = {
         "metric": "replicas/s (batched sparsification estimators)", "value": 256 / (ms * 1e-3),
-        "unit": "replicas/s", "n_gpus": 1, "steps": len(times), "warmup": 0,
+        "unit": "replicas/s", "n_gpus": 1, "steps": len(evs), "warmup": 1,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": dict(w.describe(), replicas=256, butterflies=B, kept_edges=int(kept.sum()),
-                       step="filters, compaction, union build and one count of all replicas"),
+                       step=("one replay of the HIP graph holding phase 2: every replica's "
+                             "keep flags, the union of the kept graphs, one count of all "
+                             "replicas, the estimates")),
+        "phase1_sizes_ms": phase1_ms, "eager_phase2_ms": eager_ms,
         "groups": groups,
     }
     print(json.dumps(line), flush=True)
+
+
+def capture(fn, dev):
+    """fn() captured once into a HIP graph (after one run outside the capture)."""
+    import torch
+    s = torch.cuda.Stream(dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream(dev).wait_stream(s)
+    torch.cuda.synchronize(dev)
+    hg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(hg):
+        fn()
+    torch.cuda.synchronize(dev)
+    return hg
 
 
 def bench_esamp_fast(args):
@@ -615,6 +715,8 @@ def main():
     ap.add_argument("--sampler-graph", default="chung_lu_1m_5m_50m",
                     help="graph of --workload samplers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--exact-only", action="store_true",
+                    help="the step is the plan and the exact count only (no local counts)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-uniform sampling measurement")
@@ -651,6 +753,17 @@ def main():
         return bench_side_ablation(args)
     if args.workload in ("esamp_fast", "samplers"):
         return bench_esamp_fast(args)
+    if args.workload == "learned_vs_uniform":
+        d = learned_vs_uniform(torch.device("cuda:0"), args.trials)
+        ms = d["learned"].get("gpu_ms_to_1pct")
+        print(json.dumps({
+            "metric": "GPU time to 1% rel. err at 95%, learned importance VSamp",
+            "value": ms, "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": ms, "higher_is_better": False, "scaling": "strong",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "chung_lu_20m_80m_400m learned vs uniform VSamp"},
+            "learned_vs_uniform": d}), flush=True)
+        return
     w = gen.WORKLOADS[args.workload]
     t0 = time.perf_counter()
     l, r = w.edges()
@@ -666,11 +779,12 @@ def main():
     log(f"graph built in {build_ms:.0f} ms; side={'L' if side == 1 else 'R'} wedges={W}")
 
     total = torch.zeros(1, dtype=torch.int64, device=dev)
-    cl = torch.zeros(w.nl, dtype=torch.int64, device=dev)
-    cr = torch.zeros(w.nr, dtype=torch.int64, device=dev)
-    ce = torch.zeros(w.m, dtype=torch.int64, device=dev)
+    n_out = (1, 1, 1) if args.exact_only else (w.nl, w.nr, w.m)
+    cl = torch.zeros(n_out[0], dtype=torch.int64, device=dev)
+    cr = torch.zeros(n_out[1], dtype=torch.int64, device=dev)
+    ce = torch.zeros(n_out[2], dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    ws_bytes = max(g.exact_ws_size(), g.local_ws_size())
+    ws_bytes = g.exact_ws_size() if args.exact_only else max(g.exact_ws_size(), g.local_ws_size())
     g.workspace(ws_bytes)
 
     def step(ev=None):
@@ -682,7 +796,8 @@ def main():
         g.exact_count(total)
         if ev is not None:
             ev[2].record(stream)
-        g.local_async(cl, cr, ce)
+        if not args.exact_only:
+            g.local_async(cl, cr, ce)
         if ev is not None:
             ev[3].record(stream)
 
@@ -706,11 +821,12 @@ def main():
     if got_total != ref_total:
         raise SystemExit(f"count changed between runs: {ref_total} vs {got_total}")
     # consistency of the local counts with the total (Lemma 1 and four edges per butterfly)
-    s_l = int(cl.sum().item())
-    s_r = int(cr.sum().item())
-    s_e = int(ce.sum().item())
-    if not (s_l == s_r == 2 * ref_total and s_e == 4 * ref_total):
-        raise SystemExit(f"local counts inconsistent: {s_l} {s_r} {s_e} vs B={ref_total}")
+    if not args.exact_only:
+        s_l = int(cl.sum().item())
+        s_r = int(cr.sum().item())
+        s_e = int(ce.sum().item())
+        if not (s_l == s_r == 2 * ref_total and s_e == 4 * ref_total):
+            raise SystemExit(f"local counts inconsistent: {s_l} {s_r} {s_e} vs B={ref_total}")
 
     plan_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
     exact_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
@@ -733,7 +849,7 @@ def main():
     n_all = w.nl + w.nr
     alg_local = 8 * W + 12 * w.m + 8 * n_all + 8 * (n_all + w.m)
     design_local = 16 * W + 32 * w.m + 8 * n_all + 4 * (nA + 1)
-    achieved_local = alg_local / (local_ms * 1e-3) / 1e9
+    achieved_local = alg_local / (max(local_ms, 1e-6) * 1e-3) / 1e9
     line = {
         "metric": "wedges/s + HBM GB/s (exact); GPU time to 1% rel. err, learned vs uniform vsamp",
         "value": W / (ms_per_step * 1e-3),
@@ -749,7 +865,8 @@ def main():
         "data": "synthetic",
         "config": dict(w.describe(), side="L" if side == 1 else "R", wedges=W,
                        butterflies=ref_total,
-                       step="plan + exact count + per-vertex and per-edge counts"),
+                       step=("plan + exact count" if args.exact_only else
+                             "plan + exact count + per-vertex and per-edge counts")),
         "breakdown_ms": {"plan": plan_ms, "exact_count": exact_ms, "local_counts": local_ms,
                          "graph_build_once": build_ms},
         "exact_wedges_per_s": W / (exact_ms * 1e-3),
@@ -764,6 +881,9 @@ def main():
                            "alg_bytes_per_launch": alg_local,
                            "design_bytes_per_launch": design_local},
     }
+    if args.exact_only:
+        del line["roofline_local"]
+        line["breakdown_ms"].pop("local_counts")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(w, l, r, side, args.cpu_seconds)

@@ -144,6 +144,16 @@ int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total,
 int bfc_local_ws_size(const bfc_graph *g, size_t *bytes);
 int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t *d_cnt_e,
               void *d_ws, size_t ws_bytes, hipStream_t stream);
+/* bfc_local with the part size of hub starts given: a start of more than
+ * 255 midpoints whose walk visits t wedges is cut into ceil(t / split_wedges)
+ * runs of counter windows (at most one per window, at most 4096), each
+ * walked by its own workgroup; the parts add into the start's counts and the
+ * last part to finish writes its edges.  split_wedges = 0: the default of
+ * bfc_local, 2^24.  Same results for any value. */
+int bfc_local_split_ws_size(const bfc_graph *g, uint64_t split_wedges, size_t *bytes);
+int bfc_local_split(const bfc_graph *g, uint64_t split_wedges, uint64_t *d_cnt_l,
+                    uint64_t *d_cnt_r, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes,
+                    hipStream_t stream);
 int bfc_per_vertex(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r,
                    void *d_ws, size_t ws_bytes, hipStream_t stream);
 int bfc_per_edge(const bfc_graph *g, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes,
@@ -164,22 +174,38 @@ int bfc_per_edge(const bfc_graph *g, uint64_t *d_cnt_e, void *d_ws, size_t ws_by
 /* Weighted draws (d_probs given) quantise the probabilities to integer     */
 /* weights q_j = p_j > 0 ? max(1, floor(p_j / max(p) * (2^32 - 1))) : 0 and  */
 /* take the first j whose inclusive prefix sum of q exceeds a draw below    */
-/* Q = sum(q).  These calls synchronise the stream (they read sizes or      */
-/* checks back).                                                             */
+/* Q = sum(q).  These calls only launch kernels (asynchronous, capturable   */
+/* into a HIP graph): probabilities that are negative, NaN, infinite or all */
+/* zero are detected on the device and make the estimate NaN (the draws     */
+/* then use equal weights); bfc_probs_check reports them to the host.       */
 /* ---------------------------------------------------------------------- */
+/* Synchronous check of probabilities for the weighted samplers: BFC_OK, or
+ * BFC_E_PROBS when one is negative, NaN or infinite or all are 0.  d_ws:
+ * bfc_probs_check_ws_size bytes. */
+int bfc_probs_check_ws_size(size_t *bytes);
+int bfc_probs_check(const double *d_probs, uint64_t n, void *d_ws, size_t ws_bytes,
+                    hipStream_t stream);
+/* The sparsifiers build the kept graph on the device without sorting (each
+ * CSR row filtered in order, the vertices that keep an edge renumbered in
+ * rank order: another strict total order, so the count is unchanged), lay it
+ * out on the graph's own sizes (the kept sizes never leave the device) and
+ * count it from the side ExactBFC's rule picks for the graph itself (the
+ * count is the same from either side).  Asynchronous: kernels only. */
 int bfc_spar_ws_size(const bfc_graph *g, size_t *bytes);
 /* ESpar (Sec. 6.1): keep each edge with probability p in (0, 1], count the
  * kept graph's butterflies beta exactly, estimate = beta / ((p*p)*(p*p)).
- * *d_kept_bflies = beta, *d_est = estimate (device); *kept_edges (host, may be
- * NULL) = number of kept edges.  BFC_E_ARG unless 0 < p <= 1. */
+ * *d_kept_bflies = beta, *d_est = estimate, *d_kept_edges (may be NULL) =
+ * number of kept edges (device uint64 / double / uint64).  BFC_E_ARG unless
+ * 0 < p <= 1. */
 int bfc_espar(const bfc_graph *g, double p, uint64_t seed, uint64_t *d_kept_bflies,
-              double *d_est, uint64_t *kept_edges, void *d_ws, size_t ws_bytes,
+              double *d_est, uint64_t *d_kept_edges, void *d_ws, size_t ws_bytes,
               hipStream_t stream);
 /* ClrSpar (Sec. 6.2): colour the vertices with ncolors >= 1 colours, keep the
  * monochromatic edges, count their butterflies beta exactly, estimate =
- * beta * (N * N * N) in binary64.  BFC_E_ARG if ncolors == 0. */
+ * beta * (N * N * N) in binary64; outputs as bfc_espar.  BFC_E_ARG if
+ * ncolors == 0. */
 int bfc_clrspar(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint64_t *d_mono_bflies,
-                double *d_est, uint64_t *kept_edges, void *d_ws, size_t ws_bytes,
+                double *d_est, uint64_t *d_kept_edges, void *d_ws, size_t ws_bytes,
                 hipStream_t stream);
 
 /* VSamp (Sec. 5.1): k >= 1 draws with replacement of a vertex, uniformly or
@@ -188,13 +214,23 @@ int bfc_clrspar(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint64_t *d
  * (vBFC).  *d_est: uniform: (double)sum(counts) * n / (4 k) with the sum exact
  * in uint64 (the mean of Alg. VSamp over k draws); weighted: the
  * Hansen-Hurwitz mean of B_v * Q / (4 q_v), summed left to right in blocks of
- * 1024 draws and the block sums left to right.  BFC_E_PROBS for negative,
- * NaN, infinite or all-zero probabilities; BFC_E_OVERFLOW_RISK if the uniform
- * sum overflows. */
+ * 1024 draws and the block sums left to right.  *d_est is NaN for invalid
+ * probabilities and when the exact uniform sum would overflow 64 bits. */
 int bfc_vsamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
 int bfc_vsamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
               uint32_t *d_ids, uint64_t *d_counts, double *d_est, void *d_ws, size_t ws_bytes,
               hipStream_t stream);
+/* The draws of bfc_vsamp alone, without counting: for the same graph,
+ * probabilities, k and seed, d_ids equals bfc_vsamp's.  d_weights (k uint32,
+ * may be NULL) receives each draw's integer weight w_v (1 when d_probs is
+ * NULL) and *d_total_weight (device uint64, may be NULL) the sum of all
+ * weights Q (n when uniform), so that with known counts B_v the estimate
+ * can be formed exactly as bfc_vsamp forms it.  Invalid probabilities give
+ * equal weights (check them with bfc_probs_check). */
+int bfc_vsamp_draws_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
+int bfc_vsamp_draws(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
+                    uint32_t *d_ids, uint32_t *d_weights, uint64_t *d_total_weight, void *d_ws,
+                    size_t ws_bytes, hipStream_t stream);
 /* ESamp (Sec. 5.2): the same over edges (d_probs: n_edges doubles in the
  * caller's edge order); d_eids[i] the drawn edge's index, d_counts[i] its B_e
  * (eBFC), estimate with n = n_edges. */
@@ -217,8 +253,7 @@ int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t se
  * Q / (4.0 * q_i) (weighted, as bfc_esamp), summed left to right within
  * blocks of 1024 draws, block sums left to right, divided by
  * ((double)k * (double)alpha).  BFC_E_ARG for k == 0, k >= 2^32 or
- * alpha == 0; BFC_E_PROBS as bfc_esamp.  Asynchronous without d_probs; with
- * d_probs it synchronises once to validate them. */
+ * alpha == 0; NaN estimate for invalid probabilities, as bfc_esamp. */
 int bfc_esamp_fast_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes);
 int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32_t alpha,
                    uint64_t seed, uint64_t *d_eids, uint32_t *d_hits, double *d_est,
@@ -281,7 +316,18 @@ typedef struct bfc_tuning {
     uint32_t chunk;               /* narrow starts taken from the queue at once (1..64; 4) */
     uint32_t narrow_waves_per_cu; /* narrow grid, waves per compute unit (1..8; 8) */
     uint32_t wide_groups_per_cu;  /* wide grid, workgroups per compute unit (1..2; 2) */
+    uint32_t hash_small_max;      /* narrow starts with at most this many wedges use the
+                                     one-wave hash table (1..2048; 2048; BFC_HASH_OFF: none) */
+    uint32_t hash_mid_max;        /* ... else at most this many the four-wave one
+                                     (1..16384; 16384; BFC_HASH_OFF: none) */
+    uint32_t hash_passes;         /* passes of a hash start over its wedges (1..4; 0: as many
+                                     as half-full tables need).  A pass that fills its
+                                     table hands the start to the narrow window walk */
+    uint32_t hash_max_density;    /* a start takes a hash table only when it has at most
+                                     this many wedges per counter window its end points
+                                     span (64) */
 } bfc_tuning;
+#define BFC_HASH_OFF 0xFFFFFFFFu
 
 /* bfc_exact with a given launch shape (NULL: defaults); same result. */
 int bfc_exact_tuned(const bfc_graph *g, int side, const bfc_tuning *tuning, uint64_t *d_total,
@@ -326,10 +372,11 @@ int bfc_batch_union(uint32_t ng, const uint32_t *h_nl, const uint32_t *h_nr,
 /* Replica batches: many ESpar / ClrSpar replicas of one graph counted in   */
 /* one launch.  Each replica keeps the edges its single call would keep     */
 /* (same parameters, same seed, same random stream), its kept graph becomes */
-/* one part of a disjoint union (isolated vertices dropped, ids renumbered  */
-/* densely, oriented by ExactBFC's side rule), and bfc_exact_parts counts   */
-/* all parts.  d_beta[i] and d_est[i] equal what bfc_espar / bfc_clrspar    */
-/* return for replica i, bit for bit.                                       */
+/* one part of a disjoint union (vertices without a kept edge dropped, the  */
+/* others renumbered in rank order, oriented by ExactBFC's side rule on its */
+/* own degrees), built without sorting, and bfc_exact_parts counts all      */
+/* parts.  d_beta[i] and d_est[i] equal what bfc_espar / bfc_clrspar return */
+/* for replica i, bit for bit.                                              */
 #define BFC_REPLICA_ESPAR 0
 #define BFC_REPLICA_CLRSPAR 1
 typedef struct bfc_replica {
@@ -349,10 +396,14 @@ int bfc_spar_batch_filter_ws_size(const bfc_graph *g, uint32_t nrep, size_t *byt
 int bfc_spar_batch_filter(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
                           bfc_replica_info *h_info, void *d_ws, size_t ws_bytes,
                           hipStream_t stream);
-/* Phase 2 (synchronous): the batch itself, its workspace sized exactly from
- * h_info, which must be phase 1's output for the same graph and replicas
- * (else BFC_E_ARG).  d_beta (nrep uint64) and d_est (nrep double) are device
- * arrays.  BFC_E_TOO_LARGE when the union would exceed 32-bit ids. */
+/* Phase 2: the batch itself, laid out and its workspace sized from h_info,
+ * which must be phase 1's output for the same graph and replicas.  Kernels
+ * only (asynchronous), so it can be captured into a HIP graph and replayed.
+ * On the device each replica's kept sizes are checked against h_info; if one
+ * differs, nothing is written outside the workspace and every d_beta[i] is
+ * 2^64 - 1 and every d_est[i] NaN.  d_beta (nrep uint64) and d_est (nrep
+ * double) are device arrays.  BFC_E_TOO_LARGE when the union would exceed
+ * 32-bit ids. */
 int bfc_spar_batch_ws_size(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
                            const bfc_replica_info *h_info, size_t *bytes);
 int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,

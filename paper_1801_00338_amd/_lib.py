@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbfc.so")
 
 BFC_OK = 0
+BFC_HASH_OFF = 0xFFFFFFFF
 BFC_SIDE_AUTO, BFC_SIDE_L, BFC_SIDE_R = 0, 1, 2
 ERROR_NAMES = {
     -1: "BFC_E_NULL", -2: "BFC_E_ARG", -3: "BFC_E_ID_RANGE", -4: "BFC_E_DUP_EDGE",
@@ -39,7 +40,9 @@ class bfc_graph(C.Structure):
 
 class bfc_tuning(C.Structure):
     _fields_ = [("narrow_max", C.c_uint32), ("chunk", C.c_uint32),
-                ("narrow_waves_per_cu", C.c_uint32), ("wide_groups_per_cu", C.c_uint32)]
+                ("narrow_waves_per_cu", C.c_uint32), ("wide_groups_per_cu", C.c_uint32),
+                ("hash_small_max", C.c_uint32), ("hash_mid_max", C.c_uint32),
+                ("hash_passes", C.c_uint32), ("hash_max_density", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,18 +95,28 @@ SIGNATURES = {
     "bfc_local_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
     "bfc_local": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                    C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_local_split_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)],
+                                C.c_int),
+    "bfc_local_split": ([C.POINTER(bfc_graph), C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                         C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bfc_per_vertex": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                         C.c_void_p], C.c_int),
     "bfc_per_edge": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
                      C.c_int),
+    "bfc_probs_check_ws_size": ([C.POINTER(C.c_size_t)], C.c_int),
+    "bfc_probs_check": ([C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bfc_spar_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
     "bfc_espar": ([C.POINTER(bfc_graph), C.c_double, C.c_uint64, C.c_void_p, C.c_void_p,
-                   C.POINTER(C.c_uint64), C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+                   C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bfc_clrspar": ([C.POINTER(bfc_graph), C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p,
-                     C.POINTER(C.c_uint64), C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bfc_vsamp_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
     "bfc_vsamp": ([C.POINTER(bfc_graph), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "bfc_vsamp_draws_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)],
+                                C.c_int),
+    "bfc_vsamp_draws": ([C.POINTER(bfc_graph), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
+                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "bfc_esamp_ws_size": ([C.POINTER(bfc_graph), C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
     "bfc_esamp": ([C.POINTER(bfc_graph), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),

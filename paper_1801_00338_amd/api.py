@@ -143,6 +143,25 @@ class Graph:
         check(lib().bfc_local(C.byref(self.g), ptr(cnt_l), ptr(cnt_r), ptr(cnt_e),
                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "local")
 
+    def local_split(self, split_wedges, vertices=True, edges=True):
+        """bfc_local_split: local counts with hub starts cut into parts of about
+        ``split_wedges`` wedges (same results as local())."""
+        d = self.device
+        sz = C.c_size_t()
+        check(lib().bfc_local_split_ws_size(C.byref(self.g), split_wedges, C.byref(sz)),
+              "local split ws size")
+        ws = _bytes(sz.value, d)
+        cl = torch.zeros(max(self.n_left, 1), dtype=torch.int64, device=d) if vertices else None
+        cr = torch.zeros(max(self.n_right, 1), dtype=torch.int64, device=d) if vertices else None
+        ce = torch.zeros(max(self.n_edges, 1), dtype=torch.int64, device=d) if edges else None
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        check(lib().bfc_local_split(C.byref(self.g), split_wedges, ptr(cl), ptr(cr), ptr(ce),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+              "local split")
+        torch.cuda.synchronize(d)
+        u = lambda t, n: t.cpu().numpy().view(np.uint64)[:n].copy() if t is not None else None
+        return u(cl, self.n_left), u(cr, self.n_right), u(ce, self.n_edges)
+
     def local(self, vertices=True, edges=True):
         d = self.device
         cl = torch.zeros(max(self.n_left, 1), dtype=torch.int64, device=d) if vertices else None
@@ -154,19 +173,37 @@ class Graph:
         return u(cl, self.n_left), u(cr, self.n_right), u(ce, self.n_edges)
 
     # -------------------------------------------------------------- estimators
-    def _spar(self, fn, param, seed):
-        L = lib()
+    def spar_buffers(self):
+        """Workspace and outputs (beta, estimate, kept edges) for the sparsifier calls."""
         sz = C.c_size_t()
-        check(L.bfc_spar_ws_size(C.byref(self.g), C.byref(sz)), "spar ws size")
-        ws = _bytes(sz.value, self.device)
-        beta = torch.zeros(1, dtype=torch.int64, device=self.device)
-        est = torch.zeros(1, dtype=torch.float64, device=self.device)
-        kept = C.c_uint64()
-        check(fn(C.byref(self.g), param, seed, C.c_void_p(beta.data_ptr()),
-                 C.c_void_p(est.data_ptr()), C.byref(kept), C.c_void_p(ws.data_ptr()), ws.numel(),
-                 _stream()), "sparsifier")
+        check(lib().bfc_spar_ws_size(C.byref(self.g), C.byref(sz)), "spar ws size")
+        return dict(ws=_bytes(sz.value, self.device),
+                    out=torch.zeros(3, dtype=torch.int64, device=self.device))
+
+    def _spar_async(self, fn, buf, param, seed, stream=None):
+        ws, out = buf["ws"], buf["out"]
+        check(fn(C.byref(self.g), param, seed, C.c_void_p(out.data_ptr()),
+                 C.c_void_p(out.data_ptr() + 8), C.c_void_p(out.data_ptr() + 16),
+                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "sparsifier")
+        return buf
+
+    def espar_async(self, buf, p, seed, stream=None):
+        """Queue ESpar into buf["out"] = (beta, estimate bits, kept edges)."""
+        return self._spar_async(lib().bfc_espar, buf, C.c_double(p), seed, stream)
+
+    def clrspar_async(self, buf, ncolors, seed, stream=None):
+        """Queue ClrSpar into buf["out"] = (beta, estimate bits, kept edges)."""
+        return self._spar_async(lib().bfc_clrspar, buf, ncolors, seed, stream)
+
+    @staticmethod
+    def spar_result(buf):
+        h = buf["out"].cpu().numpy()
+        return int(h.view(np.uint64)[0]), float(h[1:2].view(np.float64)[0]), int(h.view(np.uint64)[2])
+
+    def _spar(self, fn, param, seed):
+        buf = self._spar_async(fn, self.spar_buffers(), param, seed)
         torch.cuda.synchronize(self.device)
-        return int(beta.cpu().numpy().view(np.uint64)[0]), float(est.item()), kept.value
+        return self.spar_result(buf)
 
     def espar(self, p, seed):
         """ESpar: (kept butterflies, estimate, kept edges)."""
@@ -175,6 +212,15 @@ class Graph:
     def clrspar(self, ncolors, seed):
         """ClrSpar: (monochromatic butterflies, estimate, kept edges)."""
         return self._spar(lib().bfc_clrspar, ncolors, seed)
+
+    def check_probs(self, probs):
+        """bfc_probs_check (synchronous): BfcError BFC_E_PROBS for invalid probabilities."""
+        sz = C.c_size_t()
+        check(lib().bfc_probs_check_ws_size(C.byref(sz)), "probs check ws size")
+        ws = _bytes(sz.value, self.device)
+        check(lib().bfc_probs_check(C.c_void_p(probs.data_ptr()), probs.numel(),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+              "probabilities")
 
     def _samp(self, size_fn, fn, n, k, seed, probs, id_dtype):
         sz = C.c_size_t()
@@ -191,6 +237,7 @@ class Graph:
                 pt = torch.as_tensor(np.ascontiguousarray(probs, dtype=np.float64)).to(self.device)
             if pt.numel() != n:
                 raise ValueError("probs has the wrong length")
+            self.check_probs(pt)
             pp = C.c_void_p(pt.data_ptr())
         check(fn(C.byref(self.g), pp, k, seed, C.c_void_p(ids.data_ptr()),
                  C.c_void_p(cnt.data_ptr()), C.c_void_p(est.data_ptr()), C.c_void_p(ws.data_ptr()),
@@ -220,6 +267,39 @@ class Graph:
                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "vsamp")
         return buf["est"]
 
+    def vsamp_draws_buffers(self, k):
+        """Device buffers for vsamp_draws_async with k draws."""
+        sz = C.c_size_t()
+        check(lib().bfc_vsamp_draws_ws_size(C.byref(self.g), k, C.byref(sz)), "draws ws size")
+        return dict(ws=_bytes(sz.value, self.device), k=k,
+                    ids=torch.zeros(max(k, 1), dtype=torch.int32, device=self.device),
+                    w=torch.zeros(max(k, 1), dtype=torch.int32, device=self.device),
+                    total=torch.zeros(1, dtype=torch.int64, device=self.device))
+
+    def vsamp_draws_async(self, buf, seed, probs=None, stream=None):
+        """Queue VSamp's draws only (ids, integer weights, weight total)."""
+        ws = buf["ws"]
+        check(lib().bfc_vsamp_draws(C.byref(self.g),
+                                    C.c_void_p(probs.data_ptr()) if probs is not None else None,
+                                    buf["k"], seed, C.c_void_p(buf["ids"].data_ptr()),
+                                    C.c_void_p(buf["w"].data_ptr()),
+                                    C.c_void_p(buf["total"].data_ptr()),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+              "vsamp draws")
+        return buf
+
+    def vsamp_draws(self, k, seed, probs=None):
+        """VSamp's draws: (global ids, integer weights, weight total)."""
+        if probs is not None:
+            probs = torch.as_tensor(np.ascontiguousarray(probs, dtype=np.float64)
+                                    if not isinstance(probs, torch.Tensor) else probs)
+            probs = probs.to(device=self.device, dtype=torch.float64).contiguous()
+        buf = self.vsamp_draws_async(self.vsamp_draws_buffers(k), seed, probs)
+        torch.cuda.synchronize(self.device)
+        return (buf["ids"].cpu().numpy().view(np.uint32)[:k].copy(),
+                buf["w"].cpu().numpy().view(np.uint32)[:k].copy(),
+                int(buf["total"].cpu().numpy().view(np.uint64)[0]))
+
     def vsamp(self, k, seed, probs=None):
         """VSamp: (drawn global ids, their counts, estimate)."""
         L = lib()
@@ -242,8 +322,8 @@ class Graph:
                     est=torch.zeros(1, dtype=torch.float64, device=self.device))
 
     def esamp_fast_async(self, bufs, alpha, seed, probs=None, stream=None):
-        """ESamp with Fast-eBFC into ``bufs`` (from esamp_fast_buffers); no synchronisation
-        unless ``probs`` (a device float64 tensor of n_edges) is given."""
+        """ESamp with Fast-eBFC into ``bufs`` (from esamp_fast_buffers), asynchronous;
+        ``probs`` a device float64 tensor of n_edges, or None."""
         pp = None
         if probs is not None:
             if probs.numel() != self.n_edges or probs.dtype != torch.float64:
@@ -263,6 +343,7 @@ class Graph:
             probs = torch.as_tensor(np.ascontiguousarray(probs, dtype=np.float64))
         if probs is not None:
             probs = probs.to(device=self.device, dtype=torch.float64).contiguous()
+            self.check_probs(probs)
         self.esamp_fast_async(bufs, alpha, seed, probs)
         torch.cuda.synchronize(self.device)
         return (bufs["eids"].cpu().numpy().view(np.uint64)[:k].copy(),
@@ -340,10 +421,32 @@ class Graph:
         """Replicas [(kind, param, seed)] with kind "espar" (param p) or "clrspar" (param N),
         counted in one batch: (counts uint64[n], estimates float64[n], kept edges uint64[n]).
         ``log`` (optional) receives a line after each phase."""
+        rb = ReplicaBatch(self, replicas, tuning=tuning, log=log)
+        beta, est = rb.run()
+        return beta, est, rb.kept
+
+    def per_vertex(self):
+        cl, cr, _ = self.local(vertices=True, edges=False)
+        return cl, cr
+
+    def per_edge(self):
+        return self.local(vertices=False, edges=True)[2]
+
+
+class ReplicaBatch:
+    """ESpar / ClrSpar replicas of one graph counted together.
+
+    Construction runs phase 1 (each replica's kept sizes; synchronous) and
+    sizes the workspace; ``run_async`` queues phase 2 (kernels only, so it
+    may be captured into a HIP graph and replayed) into device tensors.
+    """
+
+    def __init__(self, graph, replicas, tuning=None, log=None):
         L = lib()
         log = log or (lambda msg: None)
-        n = len(replicas)
-        reps = (_lib.bfc_replica * n)()
+        self.graph = graph
+        n = self.n = len(replicas)
+        reps = self.reps = (_lib.bfc_replica * n)()
         for i, (kind, param, seed) in enumerate(replicas):
             if kind == "espar":
                 reps[i] = _lib.bfc_replica(_lib.BFC_REPLICA_ESPAR, 0, float(param), seed)
@@ -352,38 +455,38 @@ class Graph:
             else:
                 raise ValueError(kind)
         sz = C.c_size_t()
-        check(L.bfc_spar_batch_filter_ws_size(C.byref(self.g), n, C.byref(sz)), "filter ws size")
-        ws = _bytes(sz.value, self.device)
-        info = (_lib.bfc_replica_info * n)()
-        check(L.bfc_spar_batch_filter(C.byref(self.g), n, reps, info, C.c_void_p(ws.data_ptr()),
-                                      ws.numel(), _stream()), "batch filter")
+        g = C.byref(graph.g)
+        check(L.bfc_spar_batch_filter_ws_size(g, n, C.byref(sz)), "filter ws size")
+        ws = _bytes(sz.value, graph.device)
+        info = self.info = (_lib.bfc_replica_info * n)()
+        check(L.bfc_spar_batch_filter(g, n, reps, info, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream()), "batch filter")
         del ws
-        check(L.bfc_spar_batch_ws_size(C.byref(self.g), n, reps, info, C.byref(sz)),
-              "batch ws size")
-        self.last_batch_ws_bytes = sz.value
+        check(L.bfc_spar_batch_ws_size(g, n, reps, info, C.byref(sz)), "batch ws size")
+        self.ws_bytes = sz.value
+        self.kept = np.array([info[i].kept for i in range(n)], dtype=np.uint64)
         starts = sum(info[i].n_right if info[i].sumsq_left < info[i].sumsq_right
                      else info[i].n_left for i in range(n))
-        log(f"replica filter done: {sum(info[i].kept for i in range(n))} kept edges, "
+        log(f"replica filter done: {int(self.kept.sum())} kept edges, "
             f"{starts} union start vertices, workspace {sz.value / 1e9:.1f} GB")
-        ws = _bytes(sz.value, self.device)
-        kept = [info[i].kept for i in range(n)]
-        beta = torch.zeros(n, dtype=torch.int64, device=self.device)
-        est = torch.zeros(n, dtype=torch.float64, device=self.device)
-        t = _tuning(tuning)
-        check(L.bfc_spar_batch(C.byref(self.g), n, reps, info, C.byref(t) if t else None,
-                               C.c_void_p(beta.data_ptr()), C.c_void_p(est.data_ptr()),
-                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "spar batch")
-        torch.cuda.synchronize(self.device)
-        log("replica batch counted")
-        return (beta.cpu().numpy().view(np.uint64).copy(), est.cpu().numpy().copy(),
-                np.array(kept[:], dtype=np.uint64))
+        self.ws = _bytes(sz.value, graph.device)
+        self.tuning = _tuning(tuning)
 
-    def per_vertex(self):
-        cl, cr, _ = self.local(vertices=True, edges=False)
-        return cl, cr
+    def run_async(self, beta, est, stream=None):
+        """Queue phase 2: beta (int64) and est (float64) device tensors of n entries."""
+        t = self.tuning
+        check(lib().bfc_spar_batch(C.byref(self.graph.g), self.n, self.reps, self.info,
+                                   C.byref(t) if t else None, C.c_void_p(beta.data_ptr()),
+                                   C.c_void_p(est.data_ptr()), C.c_void_p(self.ws.data_ptr()),
+                                   self.ws.numel(), _stream(stream)), "spar batch")
 
-    def per_edge(self):
-        return self.local(vertices=False, edges=True)[2]
+    def run(self):
+        d = self.graph.device
+        beta = torch.zeros(self.n, dtype=torch.int64, device=d)
+        est = torch.zeros(self.n, dtype=torch.float64, device=d)
+        self.run_async(beta, est)
+        torch.cuda.synchronize(d)
+        return beta.cpu().numpy().view(np.uint64).copy(), est.cpu().numpy().copy()
 
 
 def median_of_means(x, groups, per_group, means, median, stream=None):

@@ -193,9 +193,11 @@ __device__ inline uint32_t lower_bound_glb(const uint32_t *a, uint32_t lo, uint3
 
 namespace bfc {
 // Local counts of the starts of one side (count.hip); see local_run there.
-int local_ws_size(const bfc_graph *g, int side, size_t *bytes);
+// split: wedges per part of a wide start (0: the default, 2^24).
+int local_ws_size(const bfc_graph *g, int side, size_t *bytes, uint64_t split = 0);
 int local_run(const bfc_graph *g, int side, const uint8_t *mark_rank, uint64_t *d_cnt_l,
-              uint64_t *d_cnt_r, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes, hipStream_t s);
+              uint64_t *d_cnt_r, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes, hipStream_t s,
+              uint64_t split = 0);
 // Workspace bfc_exact needs on any graph of these sizes.
 size_t exact_ws_bound(uint32_t nl, uint32_t nr, uint64_t m);
 }  // namespace bfc

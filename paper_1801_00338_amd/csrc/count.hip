@@ -58,6 +58,7 @@ struct Plan {
     const uint32_t *offA, *adjA, *xA, *offB, *adjB;
     uint32_t max_deg_A;
     uint64_t wedges;
+    uint64_t split;                     // local counts: wedges per part of a wide start (0: none)
 };
 
 static int make_plan(const bfc_graph *g, int side, Plan *p) {
@@ -68,6 +69,7 @@ static int make_plan(const bfc_graph *g, int side, Plan *p) {
     else if (side == BFC_SIDE_R) r = 1;
     else return BFC_E_ARG;
     p->start_r = r;
+    p->split = 0;
     p->m = g->n_edges;
     if (!r) {
         p->nA = g->n_left; p->nB = g->n_right;
@@ -112,26 +114,45 @@ __global__ void k_seg_fill(const uint32_t *adjB, uint64_t m, const uint32_t *seg
     }
 }
 
-// The two classes of starts each have a largest-first queue.
+// Classes of starts, each with a largest-first queue: 0 dense narrow
+// windows, 1 dense wide windows, 2 and 3 hash tables (few wedges, one wave /
+// one workgroup per start).
+constexpr int NCLASS = 4;
+constexpr uint32_t CLS_NARROW = 0, CLS_WIDE = 1, CLS_HASH1 = 2, CLS_HASH2 = 3;
 struct QueueState {
-    uint32_t bcount[2][NBUCKET];
-    uint32_t cursor[2][NBUCKET];
-    uint32_t n_items[2];
-    uint32_t head[2];                   // next item to hand out
-    uint32_t done[2];                   // workgroups finished
+    uint32_t bcount[NCLASS][NBUCKET];
+    uint32_t cursor[NCLASS][NBUCKET];
+    uint32_t n_items[NCLASS];
+    uint32_t head[NCLASS];              // next item to hand out
+    uint32_t done[NCLASS];              // workgroups finished
+    uint32_t ovf_count, ovf_head;       // hash starts handed back to the narrow walk
     unsigned long long acc;             // running total of the count
 };
 
 // Wedges of start u: sum over v in N(u) of the entries of adj_B[v] after u
 // (all entries but u itself when `all_ends`, for the local counts).
 // Bucket = bit length of that count (0 = nothing to do); class 1 = wide.
+// Class: wide when d_u > narrow_max, else hash when the wedges fit the
+// small (<= hs_max) or mid (<= hm_max) tables, else narrow.  With split != 0
+// a wide start is cut into ceil(wedges / split) parts (at most one per table
+// window and SPLIT_MAX), each an item of its own (nsplit[u] parts).
+// A narrow start takes a hash table only when it is sparse: at most
+// hl.density wedges (default HASH_DENSITY) per counter window its end points
+// span (the window walk pays about one round trip per window it touches).
+constexpr uint64_t SPLIT_WEDGES = 1ull << 24;  // local counts: wedges per part of a wide start
+constexpr uint32_t SPLIT_MAX = 4096;
+constexpr uint32_t HASH_DENSITY = 64;
 __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32_t *adjA,
                                               const uint32_t *xA, const uint32_t *offB,
+                                              const uint32_t *adjB,
                                               uint32_t nA, int all_ends, const uint8_t *mark,
-                                              uint32_t narrow_max, uint8_t *bucket,
+                                              uint32_t narrow_max, uint32_t hs_max,
+                                              uint32_t hm_max, uint32_t density,
+                                              uint64_t split,
+                                              uint16_t *bucket, uint16_t *nsplit,
                                               QueueState *q) {
-    __shared__ uint32_t hist[2][NBUCKET];
-    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
+    __shared__ uint32_t hist[NCLASS][NBUCKET];
+    for (int i = threadIdx.x; i < NCLASS * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const uint32_t wpb = blockDim.x / WAVE;
@@ -139,29 +160,48 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
         uint32_t rb = offA[u], re = offA[u + 1];
         if (mark && !mark[u]) re = rb;          // start not asked for
         unsigned long long t = 0;
+        uint32_t top = 0;                       // highest end point rank
         for (uint32_t k = rb + lane; k < re; k += WAVE) {
             uint32_t v = adjA[k];
-            t += offB[v + 1] - (all_ends ? offB[v] : xA[k]) - 1;
+            const uint32_t e = offB[v + 1];
+            t += e - (all_ends ? offB[v] : xA[k]) - 1;
+            if (hs_max | hm_max) top = max(top, adjB[e - 1]);
         }
         t = wave_sum64(t);
+        top = wave_incl_max(top);
+        top = wave_last(top);
         // a start with one midpoint shares at most one with any w: C_u[w] <= 1
         // adds nothing to a count, so it is not queued (its outputs stay 0)
         if (re - rb < 2) t = 0;
         if (lane == 0) {
             uint32_t b = t ? 64 - __clzll(t) : 0;
-            uint32_t cls = (re - rb) > narrow_max;
-            bucket[u] = (uint8_t)(b | cls << 7);
-            if (b) atomicAdd(&hist[cls][b], 1u);
+            const uint32_t span = (top >> G_SHIFT) - (u >> G_SHIFT) + 1;
+            const bool spread = t <= (uint64_t)density * span;
+            uint32_t cls = (re - rb) > narrow_max ? CLS_WIDE
+                         : !spread ? CLS_NARROW
+                         : t <= hs_max ? CLS_HASH1 : t <= hm_max ? CLS_HASH2 : CLS_NARROW;
+            uint32_t G = 1;
+            if (cls == CLS_WIDE && split) {
+                const uint32_t logw = (re - rb) <= 0xFFFFu ? 1u : 0u;
+                const uint64_t nwin = ((nA - 1) >> (G_SHIFT + logw)) + 1;
+                uint64_t gg = (t + split - 1) / split;
+                gg = gg < nwin ? gg : nwin;
+                gg = gg < SPLIT_MAX ? gg : SPLIT_MAX;
+                G = gg > 1 ? (uint32_t)gg : 1u;
+            }
+            bucket[u] = (uint16_t)(b | cls << 8);
+            if (nsplit) nsplit[u] = (uint16_t)G;
+            if (b) atomicAdd(&hist[cls][b], G);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x)
+    for (int i = threadIdx.x; i < NCLASS * NBUCKET; i += blockDim.x)
         if ((&hist[0][0])[i]) atomicAdd(&(&q->bcount[0][0])[i], (&hist[0][0])[i]);
 }
 
 // Bucket b's items start after all larger buckets (largest work first).
 __global__ void k_bucket_offsets(QueueState *q) {
-    if (threadIdx.x < 2) {
+    if (threadIdx.x < NCLASS) {
         const int c = threadIdx.x;
         uint32_t run = 0;
         for (int b = NBUCKET - 1; b >= 1; b--) {
@@ -172,32 +212,48 @@ __global__ void k_bucket_offsets(QueueState *q) {
         q->head[c] = 0;
         q->done[c] = 0;
     }
-    if (threadIdx.x == 0) q->acc = 0;
+    if (threadIdx.x == 0) {
+        q->acc = 0;
+        q->ovf_count = 0;
+        q->ovf_head = 0;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_scatter_items(const uint8_t *bucket, uint32_t nA,
-                                                       QueueState *q, uint32_t *items,
-                                                       uint32_t *items_wide) {
-    __shared__ uint32_t hist[2][NBUCKET], base[2][NBUCKET];
+struct ItemLists {
+    uint32_t *l[NCLASS];
+    uint32_t *wide_g;             // part g | parts << 16 of each wide item
+    const uint16_t *nsplit;       // parts of each start (NULL: one)
+};
+
+__global__ __launch_bounds__(256) void k_scatter_items(const uint16_t *bucket, uint32_t nA,
+                                                       QueueState *q, ItemLists items) {
+    __shared__ uint32_t hist[NCLASS][NBUCKET], base[NCLASS][NBUCKET];
     // blocks stride over chunks of blockDim.x starts (the grid is capped)
     for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x; c0 < nA;
          c0 += (uint64_t)gridDim.x * blockDim.x) {
-        for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
+        for (int i = threadIdx.x; i < NCLASS * NBUCKET; i += blockDim.x) (&hist[0][0])[i] = 0;
         __syncthreads();
         const uint64_t u = c0 + threadIdx.x;
-        uint32_t b = 0, cls = 0, local = 0;
+        uint32_t b = 0, cls = 0, local = 0, G = 1;
         if (u < nA) {
-            b = bucket[u] & 127u;
-            cls = bucket[u] >> 7;
-            if (b) local = atomicAdd(&hist[cls][b], 1u);
+            b = bucket[u] & 255u;
+            cls = bucket[u] >> 8;
+            if (cls == CLS_WIDE && items.nsplit) G = items.nsplit[u];
+            if (b) local = atomicAdd(&hist[cls][b], G);
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < 2 * NBUCKET; i += blockDim.x) {
+        for (int i = threadIdx.x; i < NCLASS * NBUCKET; i += blockDim.x) {
             uint32_t h = (&hist[0][0])[i];
             if (h) (&base[0][0])[i] = atomicAdd(&(&q->cursor[0][0])[i], h);
         }
         __syncthreads();
-        if (b) (cls ? items_wide : items)[base[cls][b] + local] = (uint32_t)u;
+        if (b) {
+            for (uint32_t g = 0; g < G; g++) {
+                const uint32_t at = base[cls][b] + local + g;
+                items.l[cls][at] = (uint32_t)u;
+                if (cls == CLS_WIDE) items.wide_g[at] = g | G << 16;
+            }
+        }
         __syncthreads();            // hist and base are reset for the next chunk
     }
 }
@@ -231,6 +287,10 @@ __device__ inline void finish_launch(QueueState *q, int cls, unsigned long long 
         }
         q->head[cls] = 0;
         q->done[cls] = 0;
+        if (cls == (int)CLS_NARROW) {       // the narrow launch drained the overflow list
+            q->ovf_count = 0;
+            q->ovf_head = 0;
+        }
         __threadfence();
     }
 }
@@ -238,10 +298,12 @@ __device__ inline void finish_launch(QueueState *q, int cls, unsigned long long 
 struct CountArgs {
     const uint32_t *offA, *adjA, *xA, *offB, *adjB;
     const uint32_t *seg1, *seg_start, *seg_win;
-    const uint32_t *items, *items_wide;
+    const uint32_t *items, *items_wide, *items_h1, *items_h2;
+    uint32_t *ovf;                      // hash starts handed back to the narrow walk
     QueueState *q;
     uint32_t nA;
     uint32_t chunk;                     // narrow starts per queue access
+    uint32_t hash_passes;               // passes of a hash start (0: from its wedges)
     unsigned long long *total;
     unsigned long long *per_start;      // butterflies found from each start (rank), or null
 };
@@ -260,14 +322,28 @@ struct LocalArgs {
     unsigned long long *cntE;     // per edge (caller order), or null
     unsigned long long *twiceB;   // 2 B_v per midpoint rank (workspace)
     int pass2;                    // edge / midpoint sums wanted (else B_u only)
+    // wide starts split over several workgroups: item it covers part
+    // wide_g[it] & 0xFFFF of wide_g[it] >> 16 (equal runs of table windows);
+    // a split start's parts add into esum_g (per adjacency position) and the
+    // last part to finish (wdone[u]) writes its edges
+    const uint32_t *wide_g;
+    uint32_t *wdone;
+    unsigned long long *esum_g;
 };
 
 // Per-midpoint state of wide starts, one slot per A-side adjacency position.
+// Indexed by the start's adjacency position k, or, with stride != 0, by
+// blockIdx.x * stride + the midpoint's index j (one slice per workgroup,
+// so several workgroups can walk parts of one start).
 struct WideScratch {
     uint32_t *pos, *seg;          // cursor: next position and its segment
     uint32_t *lim, *sw, *se;      // list end; window and end of the cursor's segment
     uint32_t *lo, *hi;            // sub-run of the current window (local counts)
     unsigned long long *esum;     // sums of final counts (local counts)
+    uint64_t stride;
+    __device__ inline uint64_t at(uint32_t j, uint32_t k) const {
+        return stride ? blockIdx.x * stride + j : k;
+    }
 };
 
 // Per-edge and per-midpoint output of one (start, midpoint) pair.
@@ -710,30 +786,55 @@ __device__ inline uint32_t wave_take(QueueState *q, int cls, uint32_t chunk) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
 }
 
+__device__ inline uint32_t wave_take_ovf(QueueState *q) {
+    uint32_t b = 0;
+    if (threadIdx.x == 0) b = atomicAdd(&q->ovf_head, 1u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+}
+
 __global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
     __shared__ WShared<false> sh;
     wclear_all(sh);
     sh.tbl[WTBL_WORDS + threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t n = a.q->n_items[0];
     unsigned long long acc = 0;
-    for (uint32_t b = wave_take(a.q, 0, a.chunk); b < n; b = wave_take(a.q, 0, a.chunk)) {
-        const uint32_t e = b + a.chunk < n ? b + a.chunk : n;
-        for (uint32_t it = b; it < e; it++) {
-            const uint32_t u = a.items[it];
-            const uint32_t rb = a.offA[u];
-            const uint32_t du = a.offA[u + 1] - rb;
-            const unsigned long long s = du <= 15u ? wave_walk<false, true>(a, sh, rb, du, false)
-                                                   : wave_walk<false, false>(a, sh, rb, du, false);
-            if (a.per_start) {
-                const unsigned long long t = wave_sum64(s);
-                if (threadIdx.x == 0) a.per_start[u] = t;
+    const uint32_t n = a.q->n_items[CLS_NARROW];
+    // the class's queue first, then the starts the hash kernels (launched
+    // before this one) handed back; one walk site keeps the code small
+    bool ovf = false;
+    uint32_t no = 0;
+    uint32_t b = wave_take(a.q, CLS_NARROW, a.chunk);
+    uint32_t e = b < n ? min(b + a.chunk, n) : b;
+    for (;;) {
+        if (b >= e) {
+            if (!ovf) {
+                b = wave_take(a.q, CLS_NARROW, a.chunk);
+                e = b < n ? min(b + a.chunk, n) : b;
+                if (b >= n) {
+                    ovf = true;
+                    no = a.q->ovf_count;
+                }
             }
-            acc += s;
+            if (ovf) {
+                b = wave_take_ovf(a.q);
+                e = b + 1;
+                if (b >= no) break;
+            }
         }
+        const uint32_t u = ovf ? a.ovf[b] : a.items[b];
+        b++;
+        const uint32_t rb = a.offA[u];
+        const uint32_t du = a.offA[u + 1] - rb;
+        const unsigned long long s = du <= 15u ? wave_walk<false, true>(a, sh, rb, du, false)
+                                               : wave_walk<false, false>(a, sh, rb, du, false);
+        if (a.per_start) {
+            const unsigned long long t = wave_sum64(s);
+            if (threadIdx.x == 0) a.per_start[u] = t;
+        }
+        acc += s;
     }
     acc = wave_sum64(acc);
-    finish_launch(a.q, 0, acc, nullptr);
+    finish_launch(a.q, CLS_NARROW, acc, nullptr);
 }
 
 __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
@@ -762,6 +863,247 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
         }
     }
     finish_launch(a.c.q, 0, 0, nullptr);
+}
+
+// ------------------------------------------------------------------ hash: sparse starts
+// A start with few wedges for the span of ranks they reach crosses many
+// nearly empty windows, each a round trip of the window walk.  Such a start
+// keeps C_u[w] in an LDS hash table instead and walks its midpoints' whole
+// suffixes in one pass: key w + 1 (0 = empty) placed by multiplicative
+// hashing with linear probing, a byte counter beside it (C_u[w] <= d_u <=
+// 255).  A compare-and-swap claims or finds the key, and the counter's old
+// value is what the pair {u, w} gains, as in the window walk.  A start with
+// more wedges than half the table takes several passes, each over the end
+// points of one hash partition (the table is cleared between passes).  A
+// pass that fills the table (only possible when a partition gets more than
+// twice its share) gives the start back to the narrow window walk, which
+// counts it from scratch.
+// Small table: one wave per start; mid table: a workgroup of four waves.
+constexpr int HS_SLOTS = 1024, HM_SLOTS = 8192;
+constexpr uint32_t HS_CAP = HS_SLOTS / 2, HM_CAP = HM_SLOTS / 2;   // entries per pass
+constexpr uint32_t HASH_PASSES = 4;
+constexpr uint32_t HS_MAX = HASH_PASSES * HS_CAP, HM_MAX = HASH_PASSES * HM_CAP;
+constexpr uint32_t HASH_FULL = 0xFFFFFFFFu;
+
+template <int NW, int S>
+struct HShared {
+    uint32_t key[S];                    // w + 1, 0 = empty
+    uint32_t cnt[S / 4];                // byte counters, four per word
+    uint32_t zero[64 * NW];             // one word per thread that stays 0
+    uint32_t pre[256], lo[256], hi[256];  // per midpoint: first piece, suffix
+    uint32_t red[NW + 1];
+    unsigned long long red64[NW];
+    uint32_t item, full;
+};
+
+template <int S>
+__device__ inline uint32_t hslot(uint32_t w) {
+    constexpr int LOG = __builtin_ctz(S);
+    return (w * 0x9E3779B1u) >> (32 - LOG);
+}
+
+// Partition of w among P passes (independent of the slot bits).
+__device__ inline uint32_t hpart(uint32_t w, uint32_t P) {
+    return (uint32_t)(((uint64_t)(w * 0x85EBCA77u) * P) >> 32);
+}
+
+// Add one to C_u[w] for the (up to) sixteen entries of a piece whose bits
+// are set in `on`; returns the sum of the counters' previous values, or
+// HASH_FULL when the table held no free slot for one of them.  Probing runs
+// in rounds: every unresolved entry issues its compare-and-swap in the same
+// round (entries without work hit the thread's zero word, which the swap of
+// 0 for 0 leaves unchanged), so a round costs one LDS round trip; then the
+// sixteen counter additions go out together.
+template <int S>
+__device__ inline uint32_t hinsert16(uint32_t *key, uint32_t *cnt, uint32_t *zero,
+                                     const uint32_t (&w)[16], uint32_t on) {
+    uint32_t h[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) h[i] = hslot<S>(w[i]);
+    uint32_t pend = on;
+    for (int round = 0; pend && round < S; round++) {
+        uint32_t prev[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            const bool p = (pend >> i) & 1u;
+            prev[i] = atomicCAS(p ? &key[h[i]] : zero, 0u, p ? w[i] + 1u : 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; i++) asm volatile("" : "+v"(prev[i]));
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            const bool p = (pend >> i) & 1u;
+            const bool done = prev[i] == 0u || prev[i] == w[i] + 1u;
+            pend &= ~((uint32_t)(p && done) << i);
+            h[i] = (p && !done) ? ((h[i] + 1u) & (uint32_t)(S - 1)) : h[i];
+        }
+    }
+    if (pend) return HASH_FULL;
+    uint32_t old[16], sft[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const bool p = (on >> i) & 1u;
+        sft[i] = (h[i] & 3u) * 8u;
+        old[i] = atomicAdd(p ? &cnt[h[i] >> 2] : zero, p ? 1u << sft[i] : 0u);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) asm volatile("" : "+v"(old[i]));
+    uint32_t g = 0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) g += (old[i] >> sft[i]) & 0xFFu;
+    return g;
+}
+
+template <int NW, int S>
+__device__ inline void hclear(HShared<NW, S> &sh) {
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    sh.zero[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < S / 4; i += 64 * NW) ((uint4 *)sh.key)[i] = z;
+    for (int i = threadIdx.x; i < S / 16; i += 64 * NW) ((uint4 *)sh.cnt)[i] = z;
+}
+
+// Last midpoint j < du whose first piece is at or before piece pi.
+__device__ inline uint32_t hsearch(const uint32_t *pre, uint32_t du, uint32_t pi) {
+    uint32_t j = 0;
+    for (uint32_t st = 1u << (31 - __clz(du)); st; st >>= 1) {
+        const uint32_t t = j + st;
+        const uint32_t pv = pre[(t <= du ? t : du) - 1];
+        j = (t <= du && pv <= pi) ? t : j;
+    }
+    return j - 1;
+}
+
+// Walk of one start (d_u <= 255) by the workgroup: returns this thread's
+// part of the start's butterflies; *full (workgroup-uniform) when a pass
+// filled the table (the partial sum is then meaningless).
+template <int NW, int S>
+__device__ unsigned long long hash_walk(const CountArgs &a, HShared<NW, S> &sh, uint32_t rb,
+                                        uint32_t du, bool &full) {
+    constexpr int NTH = 64 * NW;
+    constexpr int SL = (256 + NTH - 1) / NTH;
+    constexpr uint32_t CAP = S / 2;
+    const uint32_t tid = threadIdx.x;
+    // midpoints' suffixes (entries after u, all ranked above u) and pieces
+    uint32_t run = 0;
+    unsigned long long T = 0;
+#pragma unroll
+    for (int sl = 0; sl < SL; sl++) {
+        const uint32_t j = tid + sl * NTH;
+        uint32_t lo = 0, hi = 0;
+        if (j < du) {
+            const uint32_t k = rb + j;
+            lo = a.xA[k] + 1u;
+            hi = a.offB[a.adjA[k] + 1];
+            if (hi < lo) hi = lo;
+        }
+        const uint32_t np = hi > lo ? (((hi + 3u) >> 2) - (lo >> 2) + WK - 1) / WK : 0u;
+        T += hi - lo;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<NTH>(np, sh.red, &tot);
+        if (j < 256) {
+            sh.pre[j] = run + ex;
+            sh.lo[j] = lo;
+            sh.hi[j] = hi;
+        }
+        run += tot;
+    }
+    T = block_sum64<NTH>(T, sh.red64);          // ends with a barrier
+    const uint32_t NP = run;
+    const uint32_t pw = (uint32_t)((T + CAP - 1) / CAP);
+    const uint32_t P = a.hash_passes ? a.hash_passes : (pw > 1u ? pw : 1u);
+    unsigned long long gain = 0;
+    full = false;
+    for (uint32_t p = 0; p < P; p++) {
+        for (uint32_t r0 = 0; r0 < NP; r0 += NTH) {
+            const uint32_t pi = r0 + tid;
+            const bool valid = pi < NP;
+            const uint32_t j = hsearch(sh.pre, du, valid ? pi : 0u);
+            const uint32_t lo = sh.lo[j], hi = sh.hi[j];
+            const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * WK;
+            const uint32_t base = valid ? g0 << 2 : 0u;
+            const uint32_t len = valid ? min(hi, (g0 + WK) << 2) - lo : 0u;
+            uint4 q[WK];
+            wfetch<WK>(a.adjB, Piece{base, lo, len, INF, j}, q);
+            uint32_t w[16], on = 0;
+#pragma unroll
+            for (int k = 0; k < WK; k++) {
+                w[4 * k] = q[k].x;
+                w[4 * k + 1] = q[k].y;
+                w[4 * k + 2] = q[k].z;
+                w[4 * k + 3] = q[k].w;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                const uint32_t pos = base + i;
+                on |= (uint32_t)((pos - lo) < len && (P == 1u || hpart(w[i], P) == p)) << i;
+            }
+            const uint32_t g = hinsert16<S>(sh.key, sh.cnt, &sh.zero[threadIdx.x], w, on);
+            if (g == HASH_FULL) sh.full = 1u;
+            else gain += g;
+        }
+        __syncthreads();                        // every insert of the pass is done
+        const bool f = sh.full != 0u;
+        hclear(sh);
+        __syncthreads();
+        if (f) {
+            full = true;
+            if (tid == 0) sh.full = 0u;
+            __syncthreads();
+            return 0;
+        }
+    }
+    return gain;
+}
+
+// `chunk` items per access of the class's queue counter.
+template <int NW, int S>
+__device__ inline uint32_t group_take(HShared<NW, S> &sh, QueueState *q, uint32_t cls,
+                                      uint32_t chunk) {
+    __syncthreads();
+    if (threadIdx.x == 0) sh.item = atomicAdd(&q->head[cls], chunk);
+    __syncthreads();
+    return sh.item;
+}
+
+template <int NW, int S>
+__device__ void exact_hash(const CountArgs &a, const uint32_t *items, uint32_t cls) {
+    __shared__ HShared<NW, S> sh;
+    constexpr int NTH = 64 * NW;
+    hclear(sh);
+    if (threadIdx.x == 0) sh.full = 0u;
+    const uint32_t n = a.q->n_items[cls];
+    const uint32_t chunk = NW == 1 ? 16u : 2u;
+    unsigned long long acc = 0;
+    for (uint32_t b = group_take(sh, a.q, cls, chunk); b < n;
+         b = group_take(sh, a.q, cls, chunk)) {
+        const uint32_t e = b + chunk < n ? b + chunk : n;
+        for (uint32_t it = b; it < e; it++) {
+            const uint32_t u = items[it];
+            const uint32_t rb = a.offA[u];
+            const uint32_t du = a.offA[u + 1] - rb;
+            bool full;
+            const unsigned long long s = hash_walk<NW, S>(a, sh, rb, du, full);
+            if (full) {
+                if (threadIdx.x == 0) a.ovf[atomicAdd(&a.q->ovf_count, 1u)] = u;
+                continue;
+            }
+            if (a.per_start) {
+                const unsigned long long t = block_sum64<NTH>(s, sh.red64);
+                if (threadIdx.x == 0) a.per_start[u] = t;
+            }
+            acc += s;
+        }
+    }
+    acc = block_sum64<NTH>(acc, sh.red64);
+    finish_launch(a.q, cls, acc, nullptr);
+}
+
+__global__ __launch_bounds__(64) void k_exact_hash_small(CountArgs a) {
+    exact_hash<1, HS_SLOTS>(a, a.items_h1, CLS_HASH1);
+}
+
+__global__ __launch_bounds__(256) void k_exact_hash_mid(CountArgs a) {
+    exact_hash<4, HM_SLOTS>(a, a.items_h2, CLS_HASH2);
 }
 
 // ------------------------------------------------------------------ wide: workgroup per start
@@ -911,17 +1253,22 @@ __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass,
 // its (contiguous) segments there, at most 2^LOGW of them.
 template <bool LOCAL, int TW, int HALF, int LOGW>
 __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uint32_t rb,
-                                        uint32_t du, const WideScratch &ws, bool pass2) {
+                                        uint32_t du, const WideScratch &ws, bool pass2,
+                                        uint32_t kw_lo = 0, uint32_t kw_hi = INF) {
     static_assert((HALF ? 2 : 1) * TW == (1 << (G_SHIFT + LOGW)), "table covers one window");
     const uint32_t tid = threadIdx.x, lane = tid & (WT - 1), wv = tid / WT;
     unsigned long long sum = 0;
     uint32_t mn = INF;
     for (uint32_t j = tid; j < du; j += NT) {
         const uint32_t k = rb + j;
+        const uint64_t x = ws.at(j, k);
         const uint32_t v = a.adjA[k];
         const uint32_t pb = a.offB[v], ev = a.offB[v + 1];
         uint32_t p = LOCAL ? pb : a.xA[k] + 1, s = 0, sw = INF, se = 0;
-        if (LOCAL ? (ev - pb > 1) : (p < ev)) {
+        // windows [kw_lo, kw_hi) only: the cursor starts at the first entry
+        // of window kw_lo or later
+        if (kw_lo && p < ev) p = lower_bound_glb(a.adjB, p, ev, kw_lo << (G_SHIFT + LOGW));
+        if (LOCAL ? (ev - pb > 1 && p < ev) : (p < ev)) {
             s = a.seg1[p] - 1;
             sw = a.seg_win[s];
             se = a.seg_start[s + 1];
@@ -929,27 +1276,28 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
         } else {
             p = ev;                             // nothing to walk
         }
-        ws.pos[k] = p;
-        ws.seg[k] = s;
-        ws.lim[k] = ev;
-        ws.sw[k] = sw;
-        ws.se[k] = se;
-        if (LOCAL) ws.esum[k] = 0;
+        ws.pos[x] = p;
+        ws.seg[x] = s;
+        ws.lim[x] = ev;
+        ws.sw[x] = sw;
+        ws.se[x] = se;
+        if (LOCAL) ws.esum[x] = 0;
     }
     uint32_t kw = block_min<NT>(mn, sh.red);
-    while (kw != INF) {
+    while (kw < kw_hi) {                        // INF >= kw_hi: no window left
         const uint32_t wb = kw << (G_SHIFT + LOGW);
         uint32_t next = INF;
         for (uint32_t cb = wv * WT; cb < du; cb += NT) {
             const uint32_t j = cb + lane, k = rb + j;
+            const uint64_t x = ws.at(j, k);
             uint32_t lo = 0, hi = 0, skip = INF;
             if (j < du) {
                 // the cursor in one round of independent loads
-                const uint32_t ev = ws.lim[k];
-                uint32_t p = ws.pos[k], s = ws.seg[k], sw = ws.sw[k];
+                const uint32_t ev = ws.lim[x];
+                uint32_t p = ws.pos[x], s = ws.seg[x], sw = ws.sw[x];
                 if (p < ev && (sw >> LOGW) == kw) {
                     lo = p;
-                    uint32_t e = ws.se[k], nsw = INF, nse = 0;
+                    uint32_t e = ws.se[x], nsw = INF, nse = 0;
                     s++;
                     if (e < ev) {
                         nsw = a.seg_win[s];
@@ -966,16 +1314,16 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                     hi = e < ev ? e : ev;
                     p = hi;
                     sw = p < ev ? nsw : INF;
-                    ws.pos[k] = p;
-                    ws.seg[k] = s;
-                    ws.sw[k] = sw;
-                    ws.se[k] = nse;
+                    ws.pos[x] = p;
+                    ws.seg[x] = s;
+                    ws.sw[x] = sw;
+                    ws.se[x] = nse;
                 }
                 if (p < ev) next = min(next, sw >> LOGW);
                 if (LOCAL) {
                     skip = a.xA[k];
-                    ws.lo[k] = lo;
-                    ws.hi[k] = hi;
+                    ws.lo[x] = lo;
+                    ws.hi[x] = hi;
                 }
             }
             unsigned long long unused;
@@ -985,15 +1333,16 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
             __syncthreads();                    // all counts of the window are final
             for (uint32_t cb = wv * WT; cb < du; cb += NT) {
                 const uint32_t j = cb + lane, k = rb + j;
+                const uint64_t x = ws.at(j, k);
                 uint32_t lo = 0, hi = 0, skip = INF;
                 if (j < du) {
-                    lo = ws.lo[k];
-                    hi = ws.hi[k];
+                    lo = ws.lo[x];
+                    hi = ws.hi[x];
                     skip = a.xA[k];
                 }
                 unsigned long long e = 0;
                 chunk_walk<TW, HALF>(a, sh, 1, lo, hi, skip, wb, sum, e);
-                if (j < du && e) ws.esum[k] += e;
+                if (j < du && e) ws.esum[x] += e;
             }
         }
         __syncthreads();
@@ -1040,33 +1389,66 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
 // over 2^14.
 __global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a, WideScratch ws) {
     __shared__ SharedT<TBL_WORDS_L> sh;
+    __shared__ uint32_t last;
     clear_table(sh);
     sh.tbl[TBL_WORDS_L + threadIdx.x] = 0;
-    const uint32_t n = a.c.q->n_items[1];
+    const uint32_t n = a.c.q->n_items[CLS_WIDE];
     const uint32_t tid = threadIdx.x;
     for (uint32_t it = block_take(sh, a.c.q); it < n; it = block_take(sh, a.c.q)) {
         const uint32_t u = a.c.items_wide[it];
+        const uint32_t gG = a.wide_g[it], g = gG & 0xFFFFu, G = gG >> 16;
         const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
+        const uint32_t logw = du <= 0xFFFFu ? 1u : 0u;
+        const uint32_t nwin = ((a.c.nA - 1) >> (G_SHIFT + logw)) + 1;
+        const uint32_t kw_lo = (uint32_t)((uint64_t)g * nwin / G);
+        const uint32_t kw_hi = g + 1 == G ? INF : (uint32_t)((uint64_t)(g + 1) * nwin / G);
         unsigned long long s =
-            du <= 0xFFFFu ? walk_wide<true, TBL_WORDS_L, 1, 1>(a.c, sh, rb, du, ws, a.pass2)
-                          : walk_wide<true, TBL_WORDS_L, 0, 0>(a.c, sh, rb, du, ws, a.pass2);
+            du <= 0xFFFFu
+                ? walk_wide<true, TBL_WORDS_L, 1, 1>(a.c, sh, rb, du, ws, a.pass2, kw_lo, kw_hi)
+                : walk_wide<true, TBL_WORDS_L, 0, 0>(a.c, sh, rb, du, ws, a.pass2, kw_lo, kw_hi);
         __syncthreads();
+        s = block_sum64<NT>(s, sh.red64);
+        if (G == 1) {
+            if (a.pass2) {
+                for (uint32_t j = tid; j < du; j += NT) {
+                    const uint32_t k = rb + j;
+                    const uint32_t v = a.c.adjA[k];
+                    emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], ws.esum[ws.at(j, k)]);
+                }
+            }
+            if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = s;
+            continue;
+        }
+        // one part of a split start
         if (a.pass2) {
+            for (uint32_t j = tid; j < du; j += NT) {
+                const unsigned long long e = ws.esum[ws.at(j, rb + j)];
+                if (e) atomicAdd(&a.esum_g[rb + j], e);
+            }
+        }
+        if (tid == 0 && a.cntA && s) atomicAdd(&a.cntA[a.idA[u]], s);
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            last = atomicAdd(&a.wdone[u], 1u) == G - 1;
+        }
+        __syncthreads();
+        if (last && a.pass2) {
+            __threadfence();
             for (uint32_t j = tid; j < du; j += NT) {
                 const uint32_t k = rb + j;
                 const uint32_t v = a.c.adjA[k];
-                emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], ws.esum[k]);
+                emit_edge(a, k, v, a.c.offB[v + 1] - a.c.offB[v], atomicAdd(&a.esum_g[k], 0ull));
             }
         }
-        s = block_sum64<NT>(s, sh.red64);
-        if (tid == 0 && a.cntA) a.cntA[a.idA[u]] = s;
     }
-    finish_launch(a.c.q, 1, 0, nullptr);
+    finish_launch(a.c.q, CLS_WIDE, 0, nullptr);
 }
 
 // Per-part totals of a disjoint union counted from L: part q owns the L ids
 // [part_l[q], part_l[q + 1]); its total is the sum of its starts' counts,
 // added in a fixed order (strided per thread, then the block reduction).
+// rank_l == NULL: the ids are the ranks.
 __global__ __launch_bounds__(256) void k_part_sums(const unsigned long long *per_start,
                                                    const uint32_t *rank_l, const uint32_t *part_l,
                                                    uint32_t nparts, unsigned long long *totals) {
@@ -1074,7 +1456,7 @@ __global__ __launch_bounds__(256) void k_part_sums(const unsigned long long *per
     for (uint32_t q = blockIdx.x; q < nparts; q += gridDim.x) {
         unsigned long long t = 0;
         for (uint32_t id = part_l[q] + threadIdx.x; id < part_l[q + 1]; id += blockDim.x)
-            t += per_start[rank_l[id]];
+            t += per_start[rank_l ? rank_l[id] : id];
         t = block_sum64<256>(t, red);
         if (threadIdx.x == 0) totals[q] = t;
     }
@@ -1090,11 +1472,19 @@ __global__ void k_local_finish(const unsigned long long *twiceB, const uint32_t 
 
 // ------------------------------------------------------------------ host side
 struct ExactWs {
-    uint32_t *seg1, *seg_start, *seg_win, *scan_tmp, *items, *items_wide;
+    uint32_t *seg1, *seg_start, *seg_win, *scan_tmp, *items, *items_wide, *items_h1, *items_h2;
+    uint32_t *ovf, *wide_g, *wdone;
     uint32_t *wpos, *wseg, *wlim, *wsw, *wse;
-    uint8_t *bucket;
+    uint16_t *bucket, *nsplit;
     QueueState *q;
 };
+
+// Items of the wide class: one per start, plus the extra parts of split
+// starts (at most 2 * wedges / SPLIT_WEDGES in all: every start's all-ends
+// wedges add up to twice the wedges).
+static inline size_t wide_items_cap(const Plan &p) {
+    return pad64(p.nA) + (p.split ? (size_t)(2 * (p.wedges / p.split)) : 0) + 64;
+}
 
 static ExactWs carve_exact(Carver &c, const Plan &p) {
     ExactWs w;
@@ -1103,13 +1493,19 @@ static ExactWs carve_exact(Carver &c, const Plan &p) {
     w.seg_win = c.take<uint32_t>(pad64(p.m + 2));
     w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(p.m));
     w.items = c.take<uint32_t>(pad64(p.nA));
-    w.items_wide = c.take<uint32_t>(pad64(p.nA));
+    w.items_wide = c.take<uint32_t>(wide_items_cap(p));
+    w.wide_g = c.take<uint32_t>(wide_items_cap(p));
+    w.wdone = c.take<uint32_t>(pad64(p.nA));
+    w.nsplit = c.take<uint16_t>(pad64(p.nA));
+    w.items_h1 = c.take<uint32_t>(pad64(p.nA));
+    w.items_h2 = c.take<uint32_t>(pad64(p.nA));
+    w.ovf = c.take<uint32_t>(pad64(p.nA));
     w.wpos = c.take<uint32_t>(pad64(p.m));
     w.wseg = c.take<uint32_t>(pad64(p.m));
     w.wlim = c.take<uint32_t>(pad64(p.m));
     w.wsw = c.take<uint32_t>(pad64(p.m));
     w.wse = c.take<uint32_t>(pad64(p.m));
-    w.bucket = c.take<uint8_t>(pad64(p.nA));
+    w.bucket = c.take<uint16_t>(pad64(p.nA));
     w.q = c.take<QueueState>(1);
     return w;
 }
@@ -1130,8 +1526,15 @@ static bool overflow_risk(uint64_t wedges, uint32_t max_deg) {
 }
 
 // Segments, per-start work buckets and the work queues for one plan.
+// Wedge limits of the two hash classes (0: none; the local counts use none).
+struct HashLimits {
+    uint32_t small, mid, density;
+};
+constexpr HashLimits HASH_DEFAULT = {HS_MAX, HM_MAX, HASH_DENSITY}, HASH_NONE = {0, 0, 0};
+
 static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark, hipStream_t s,
-                   uint32_t narrow_max = NARROW_MAX) {
+                   uint32_t narrow_max = NARROW_MAX, HashLimits hl = HASH_NONE,
+                   uint64_t split = 0) {
     k_zero_u32<<<1, 256, 0, s>>>((uint32_t *)w.q, (uint64_t)(sizeof(QueueState) / 4));
     if (p.m) {
         k_seg_flags<<<grid_for(p.m), 256, 0, s>>>(p.adjB, p.m, w.seg1);
@@ -1144,13 +1547,18 @@ static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark,
     if (p.nA) {
         unsigned g = grid_for(p.nA, 4);
         if (g > 8192) g = 8192;
-        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.nA, all_ends, mark, narrow_max,
-                                 w.bucket, w.q);
+        k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.adjB, p.nA, all_ends, mark,
+                                 narrow_max,
+                                 hl.small, hl.mid, hl.density, split, w.bucket,
+                                 split ? w.nsplit : nullptr,
+                                 w.q);
         BFC_HIP(hipGetLastError());
     }
     k_bucket_offsets<<<1, 64, 0, s>>>(w.q);
     if (p.nA)
-        k_scatter_items<<<grid_for(p.nA), 256, 0, s>>>(w.bucket, p.nA, w.q, w.items, w.items_wide);
+        k_scatter_items<<<grid_for(p.nA), 256, 0, s>>>(
+            w.bucket, p.nA, w.q, ItemLists{{w.items, w.items_wide, w.items_h1, w.items_h2},
+                                           w.wide_g, split ? w.nsplit : nullptr});
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
@@ -1158,8 +1566,9 @@ static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark,
 static void fill_args(const Plan &p, const ExactWs &w, CountArgs &a) {
     a.offA = p.offA; a.adjA = p.adjA; a.xA = p.xA; a.offB = p.offB; a.adjB = p.adjB;
     a.seg1 = w.seg1; a.seg_start = w.seg_start; a.seg_win = w.seg_win;
-    a.items = w.items; a.items_wide = w.items_wide; a.q = w.q; a.nA = p.nA; a.total = nullptr;
-    a.chunk = WCHUNK; a.per_start = nullptr;
+    a.items = w.items; a.items_wide = w.items_wide; a.items_h1 = w.items_h1;
+    a.items_h2 = w.items_h2; a.ovf = w.ovf; a.q = w.q; a.nA = p.nA; a.total = nullptr;
+    a.chunk = WCHUNK; a.per_start = nullptr; a.hash_passes = 0;
 }
 
 // Tuning with defaults filled in and ranges checked.
@@ -1168,20 +1577,34 @@ static int resolve_tuning(const bfc_tuning *t, bfc_tuning &r) {
     r.chunk = WCHUNK;
     r.narrow_waves_per_cu = 8;
     r.wide_groups_per_cu = 2;
+    r.hash_small_max = HS_MAX;
+    r.hash_mid_max = HM_MAX;
+    r.hash_passes = 0;
+    r.hash_max_density = HASH_DENSITY;
     if (!t) return BFC_OK;
+    r.hash_passes = t->hash_passes;
+    if (t->hash_max_density) r.hash_max_density = t->hash_max_density;
     if (t->narrow_max) r.narrow_max = t->narrow_max;
     if (t->chunk) r.chunk = t->chunk;
     if (t->narrow_waves_per_cu) r.narrow_waves_per_cu = t->narrow_waves_per_cu;
     if (t->wide_groups_per_cu) r.wide_groups_per_cu = t->wide_groups_per_cu;
+    if (t->hash_small_max) r.hash_small_max = t->hash_small_max == BFC_HASH_OFF ? 0 : t->hash_small_max;
+    if (t->hash_mid_max) r.hash_mid_max = t->hash_mid_max == BFC_HASH_OFF ? 0 : t->hash_mid_max;
     if (r.narrow_max > NARROW_MAX || r.chunk > 64 || r.narrow_waves_per_cu > 8 ||
-        r.wide_groups_per_cu > 2)
+        r.wide_groups_per_cu > 2 || r.hash_small_max > HS_MAX || r.hash_mid_max > HM_MAX ||
+        r.hash_passes > HASH_PASSES)
         return BFC_E_ARG;
     return BFC_OK;
 }
 
+static HashLimits hash_limits(const bfc_tuning &r) {
+    return HashLimits{r.hash_small_max, r.hash_mid_max, r.hash_max_density};
+}
+
 // Waves of the narrow grid per CU (LDS bound: eight 16 KiB tables) and
 // workgroups of the wide grid (two 64 KiB tables).
-static int grids(unsigned &narrow, unsigned &wide, const bfc_tuning *t = nullptr) {
+static int grids(unsigned &narrow, unsigned &wide, const bfc_tuning *t = nullptr,
+                 unsigned *hsmall = nullptr, unsigned *hmid = nullptr) {
     bfc_tuning r;
     BFC_TRY(resolve_tuning(t, r));
     int dev = 0;
@@ -1189,6 +1612,9 @@ static int grids(unsigned &narrow, unsigned &wide, const bfc_tuning *t = nullptr
     const unsigned cu = (unsigned)device_cu_count(dev);
     narrow = cu * r.narrow_waves_per_cu;
     wide = cu * r.wide_groups_per_cu;
+    // hash kernels: 8.2 KiB of LDS per one-wave group, 44 KiB per mid group
+    if (hsmall) *hsmall = cu * 16;
+    if (hmid) *hmid = cu * 3;
     return BFC_OK;
 }
 
@@ -1204,20 +1630,38 @@ static int exact_setup(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes
     return BFC_OK;
 }
 
+// Local counts: the exact count's workspace, the midpoint sums, the edge
+// sums of split starts, and each wide workgroup's slice of cursor state.
 struct LocalWs {
     ExactWs e;
-    unsigned long long *twiceB, *esum;
-    uint32_t *wlo, *whi;
+    unsigned long long *twiceB, *esum_g;
+    WideScratch slices;
 };
 
-static LocalWs carve_local(Carver &c, const Plan &p) {
+static LocalWs carve_local(Carver &c, const Plan &p, unsigned wide_groups) {
     LocalWs w;
     w.e = carve_exact(c, p);
     w.twiceB = c.take<unsigned long long>(pad64(p.nB));
-    w.esum = c.take<unsigned long long>(pad64(p.m));
-    w.wlo = c.take<uint32_t>(pad64(p.m));
-    w.whi = c.take<uint32_t>(pad64(p.m));
+    w.esum_g = c.take<unsigned long long>(pad64(p.m));
+    const uint64_t stride = pad64(p.max_deg_A);
+    const uint64_t n = (uint64_t)wide_groups * stride;
+    WideScratch &x = w.slices;
+    x.pos = c.take<uint32_t>(n);
+    x.seg = c.take<uint32_t>(n);
+    x.lim = c.take<uint32_t>(n);
+    x.sw = c.take<uint32_t>(n);
+    x.se = c.take<uint32_t>(n);
+    x.lo = c.take<uint32_t>(n);
+    x.hi = c.take<uint32_t>(n);
+    x.esum = c.take<unsigned long long>(n);
+    x.stride = stride;
     return w;
+}
+
+// Workgroups of the local counts' wide grid (default launch shape).
+static int local_wide_groups(unsigned &gw) {
+    unsigned gn;
+    return grids(gn, gw);
 }
 
 // Workspace of bfc_exact for any graph with these sizes (either side).
@@ -1231,12 +1675,15 @@ size_t exact_ws_bound(uint32_t nl, uint32_t nr, uint64_t m) {
     return c.used;
 }
 
-int local_ws_size(const bfc_graph *g, int side, size_t *bytes) {
+int local_ws_size(const bfc_graph *g, int side, size_t *bytes, uint64_t split) {
     if (!bytes) return BFC_E_NULL;
     Plan p;
     BFC_TRY(make_plan(g, side, &p));
+    p.split = split ? split : SPLIT_WEDGES;
+    unsigned gw;
+    BFC_TRY(local_wide_groups(gw));
     Carver c(nullptr, 0);
-    carve_local(c, p);
+    carve_local(c, p, gw);
     *bytes = c.used;
     return BFC_OK;
 }
@@ -1247,21 +1694,27 @@ int local_ws_size(const bfc_graph *g, int side, size_t *bytes) {
 // (from the processed starts' edges only).
 int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt_l,
               uint64_t *d_cnt_r, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes,
-              hipStream_t s) {
+              hipStream_t s, uint64_t split) {
     if (!d_ws || (!d_cnt_l && !d_cnt_r && !d_cnt_e)) return BFC_E_NULL;
     Plan p;
     BFC_TRY(make_plan(g, side, &p));
+    p.split = split ? split : SPLIT_WEDGES;
     if (!aligned256(d_ws)) return BFC_E_ALIGN;
     if (p.wedges >> 63 || overflow_risk(2 * p.wedges, p.max_deg_A)) return BFC_E_OVERFLOW_RISK;
+    unsigned gn, gw;
+    BFC_TRY(grids(gn, gw));
     Carver c(d_ws, ws_bytes);
-    LocalWs w = carve_local(c, p);
+    LocalWs w = carve_local(c, p, gw);
     if (!c.fits()) return BFC_E_WS_SMALL;
     unsigned long long *cl = (unsigned long long *)d_cnt_l, *cr = (unsigned long long *)d_cnt_r,
                        *ce = (unsigned long long *)d_cnt_e;
     unsigned long long *cntB = p.start_r ? cl : cr;
+    const bool pass2 = ce != nullptr || cntB != nullptr;
     k_zero_u64<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.nB);
+    k_zero_u32<<<grid_for(p.nA), 256, 0, s>>>(w.e.wdone, p.nA);
+    if (pass2) k_zero_u64<<<grid_for(p.m), 256, 0, s>>>(w.esum_g, p.m);
     BFC_HIP(hipGetLastError());
-    BFC_TRY(prepare(p, w.e, 1, mark, s));
+    BFC_TRY(prepare(p, w.e, 1, mark, s, NARROW_MAX, HASH_NONE, p.split));
     if (p.nA == 0 || p.m == 0) return BFC_OK;
     LocalArgs a;
     fill_args(p, w.e, a.c);
@@ -1270,12 +1723,12 @@ int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt
     a.cntA = p.start_r ? cr : cl;
     a.cntE = ce;
     a.twiceB = w.twiceB;
-    a.pass2 = (ce != nullptr || cntB != nullptr);
-    WideScratch ws = {w.e.wpos, w.e.wseg, w.e.wlim, w.e.wsw, w.e.wse, w.wlo, w.whi, w.esum};
-    unsigned gn, gw;
-    BFC_TRY(grids(gn, gw));
+    a.pass2 = pass2;
+    a.wide_g = w.e.wide_g;
+    a.wdone = w.e.wdone;
+    a.esum_g = w.esum_g;
     k_local_narrow<<<gn, WT, 0, s>>>(a);
-    k_local_wide<<<gw, NT, 0, s>>>(a, ws);
+    k_local_wide<<<gw, NT, 0, s>>>(a, w.slices);
     if (cntB)
         k_local_finish<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.start_r ? g->id_l : g->id_r,
                                                        p.nB, cntB);
@@ -1296,12 +1749,16 @@ static int launch_count(const Plan &p, const ExactWs &w, const bfc_tuning *t,
     CountArgs a;
     fill_args(p, w, a);
     a.chunk = r.chunk;
+    a.hash_passes = r.hash_passes;
     a.per_start = per_start;
-    unsigned gn, gw;
-    BFC_TRY(grids(gn, gw, &r));
+    unsigned gn, gw, ghs, ghm;
+    BFC_TRY(grids(gn, gw, &r, &ghs, &ghm));
+    // hash starts first: a start they give back is walked by the narrow launch
+    k_exact_hash_small<<<ghs, 64, 0, s>>>(a);
+    k_exact_hash_mid<<<ghm, 256, 0, s>>>(a);
     k_exact_narrow<<<gn, WT, 0, s>>>(a);
     a.total = total;
-    WideScratch ws = {w.wpos, w.wseg, w.wlim, w.wsw, w.wse, nullptr, nullptr, nullptr};
+    WideScratch ws = {w.wpos, w.wseg, w.wlim, w.wsw, w.wse, nullptr, nullptr, nullptr, 0};
     k_exact_wide<<<gw, NT, 0, s>>>(a, ws);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
@@ -1341,7 +1798,7 @@ int bfc_exact_plan(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes, hi
     Plan p;
     ExactWs w;
     BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
-    return prepare(p, w, 0, nullptr, s);
+    return prepare(p, w, 0, nullptr, s, NARROW_MAX, HASH_DEFAULT);
 }
 
 int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total, void *d_ws,
@@ -1370,7 +1827,7 @@ int bfc_exact_tuned(const bfc_graph *g, int side, const bfc_tuning *t, uint64_t 
     Plan p;
     ExactWs w;
     BFC_TRY(exact_setup(g, side, d_ws, ws_bytes, p, w));
-    BFC_TRY(prepare(p, w, 0, nullptr, s, r.narrow_max));
+    BFC_TRY(prepare(p, w, 0, nullptr, s, r.narrow_max, hash_limits(r)));
     return launch_count(p, w, &r, (unsigned long long *)d_total, nullptr, s);
 }
 
@@ -1404,7 +1861,7 @@ int bfc_exact_parts(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_
     if (!c.fits()) return BFC_E_WS_SMALL;
     k_zero_u64<<<grid_for(p.nA), 256, 0, s>>>(per_start, p.nA);
     BFC_HIP(hipGetLastError());
-    BFC_TRY(prepare(p, w, 0, nullptr, s, r.narrow_max));
+    BFC_TRY(prepare(p, w, 0, nullptr, s, r.narrow_max, hash_limits(r)));
     BFC_TRY(launch_count(p, w, &r, total, per_start, s));
     unsigned gp = nparts < 65535u ? nparts : 65535u;
     k_part_sums<<<gp, 256, 0, s>>>(per_start, g->rank_l, d_part_l, nparts,
@@ -1425,9 +1882,11 @@ int bfc_autotune_ws_size(const bfc_graph *g, size_t *bytes) {
 
 // Times candidate tunings on this graph (nparts == 0: bfc_exact_tuned with
 // the automatic side) or this batch (bfc_exact_parts) and returns the
-// fastest.  Two stages: the narrow/wide threshold with the queue chunk, then
-// the grid shapes for the best of those.  Each candidate runs once untimed
-// and three times timed with events on the stream; the minimum counts.
+// fastest.  Three stages: the narrow/wide threshold with the queue chunk,
+// the grid shapes for the best of those, then the hash tables of sparse
+// starts (off, or at most 16, 64 or 256 wedges per spanned window).  Each candidate runs
+// once untimed and three times timed with events on the stream; the minimum
+// counts.
 int bfc_autotune(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_l,
                  uint64_t *d_totals, void *d_ws, size_t ws_bytes, hipStream_t s,
                  bfc_tuning *best, float *best_ms) {
@@ -1485,6 +1944,24 @@ int bfc_autotune(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_l,
                 if (ms < cur_ms) { cur_ms = ms; cur = t; }
             }
     }
+    {
+        // hash tables for sparse starts: off, or up to 16, 64 or 256 wedges per window
+        const uint32_t hd[] = {0, 16, 64, 256};
+        const bfc_tuning base = cur;
+        for (uint32_t d : hd) {
+            bfc_tuning t = base;
+            if (d == 0) {
+                t.hash_small_max = t.hash_mid_max = BFC_HASH_OFF;
+            } else {
+                t.hash_max_density = d;
+            }
+            if (d == HASH_DENSITY && base.hash_max_density == 0 && base.hash_small_max == 0)
+                continue;                       // the defaults: timed already
+            float ms;
+            if ((rc = time_one(t, ms)) != BFC_OK) goto out;
+            if (ms < cur_ms) { cur_ms = ms; cur = t; }
+        }
+    }
     *best = cur;
     if (best_ms) *best_ms = cur_ms;
 out:
@@ -1494,7 +1971,27 @@ out:
 }
 
 int bfc_local_ws_size(const bfc_graph *g, size_t *bytes) {
-    return bfc::local_ws_size(g, BFC_SIDE_AUTO, bytes);
+    return bfc::local_ws_size(g, BFC_SIDE_AUTO, bytes, 0);
+}
+
+int bfc_local_split_ws_size(const bfc_graph *g, uint64_t split_wedges, size_t *bytes) {
+    return bfc::local_ws_size(g, BFC_SIDE_AUTO, bytes, split_wedges);
+}
+
+int bfc_local_split(const bfc_graph *g, uint64_t split_wedges, uint64_t *d_cnt_l,
+                    uint64_t *d_cnt_r, uint64_t *d_cnt_e, void *d_ws, size_t ws_bytes,
+                    hipStream_t s) {
+    if (!g || !d_ws || (!d_cnt_l && !d_cnt_r && !d_cnt_e)) return BFC_E_NULL;
+    if (((uintptr_t)d_cnt_l & 7) || ((uintptr_t)d_cnt_r & 7) || ((uintptr_t)d_cnt_e & 7))
+        return BFC_E_ALIGN;
+    unsigned long long *cl = (unsigned long long *)d_cnt_l, *cr = (unsigned long long *)d_cnt_r,
+                       *ce = (unsigned long long *)d_cnt_e;
+    if (cl) k_zero_u64<<<grid_for(g->n_left), 256, 0, s>>>(cl, g->n_left);
+    if (cr) k_zero_u64<<<grid_for(g->n_right), 256, 0, s>>>(cr, g->n_right);
+    if (ce) k_zero_u64<<<grid_for(g->n_edges), 256, 0, s>>>(ce, g->n_edges);
+    BFC_HIP(hipGetLastError());
+    return bfc::local_run(g, BFC_SIDE_AUTO, nullptr, d_cnt_l, d_cnt_r, d_cnt_e, d_ws, ws_bytes, s,
+                          split_wedges);
 }
 
 int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t *d_cnt_e,
@@ -1508,7 +2005,8 @@ int bfc_local(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, uint64_t
     if (cr) k_zero_u64<<<grid_for(g->n_right), 256, 0, s>>>(cr, g->n_right);
     if (ce) k_zero_u64<<<grid_for(g->n_edges), 256, 0, s>>>(ce, g->n_edges);
     BFC_HIP(hipGetLastError());
-    return bfc::local_run(g, BFC_SIDE_AUTO, nullptr, d_cnt_l, d_cnt_r, d_cnt_e, d_ws, ws_bytes, s);
+    return bfc::local_run(g, BFC_SIDE_AUTO, nullptr, d_cnt_l, d_cnt_r, d_cnt_e, d_ws, ws_bytes, s,
+                          0);
 }
 
 int bfc_per_vertex(const bfc_graph *g, uint64_t *d_cnt_l, uint64_t *d_cnt_r, void *d_ws,

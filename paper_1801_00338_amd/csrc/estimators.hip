@@ -82,57 +82,165 @@ __device__ inline uint32_t colour_of(uint64_t seed, uint32_t side, uint32_t v, u
 }
 
 // ------------------------------------------------------------------ sparsifier kernels
-// Every L row, one wave per row: the keep flag of each edge (l, r) by ids.
-struct FilterArgs {
-    const uint32_t *off_l, *adj_l, *id_l, *id_r;
-    uint32_t nl;
+// A sparsifier keeps a subset of the edges, and its estimate is the exact
+// count of the kept graph.  The kept graph is built without sorting:
+// filtering a CSR row keeps its order, and the ranks restricted to the
+// vertices that keep an edge are still a strict total order (any such order
+// counts every same-side pair once), so the kept graph's CSRs are
+// compactions of the graph's own, each kept vertex renumbered to the number
+// of kept vertices ranked below it.
+
+// One replica's keep rule: ESpar by a Philox threshold on the edge's ids,
+// ClrSpar by equal colours of its ends.
+struct KeepRule {
     int kind;                   // 0 = ESpar, 1 = ClrSpar
-    uint64_t seed, thresh;      // ESpar: keep iff x < thresh (keep_all overrides)
-    int keep_all;
-    const uint32_t *col_l, *col_r;  // ClrSpar colours by id
+    int keep_all;               // p = 1 or N = 1
+    uint64_t seed, thresh;      // ESpar: keep iff x < thresh
+    const uint32_t *col_l, *col_r;  // ClrSpar colours by rank
 };
 
-__device__ inline uint32_t keep_edge(const FilterArgs &f, uint32_t l, uint32_t r) {
-    if (f.keep_all) return 1u;
-    if (f.kind == 0) {
+// One side of the graph as the kept-graph builder reads it.
+struct SideView {
+    const uint32_t *off, *adj, *xpos;   // rows by rank, neighbour ranks, cross positions
+    const uint32_t *id, *id_o;          // ids of this side's and the other side's ranks
+    uint32_t n;
+    int is_r;                           // rows are R vertices (the rule takes (l, r))
+};
+
+// Keep decision of the edge between this side's rank u and the other
+// side's rank w.
+__device__ inline uint32_t keep_edge(const KeepRule &k, const SideView &v, uint32_t u,
+                                     uint32_t w) {
+    if (k.keep_all) return 1u;
+    if (k.kind == 0) {
+        const uint32_t a = v.id[u], b = v.id_o[w];
         uint32_t o[4];
-        philox(l, r, TAG_ESPAR, 0, f.seed, o);
+        philox(v.is_r ? b : a, v.is_r ? a : b, TAG_ESPAR, 0, k.seed, o);
         const uint64_t x = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
-        return x < f.thresh;
+        return x < k.thresh;
     }
-    return f.col_l[l] == f.col_r[r];
+    return v.is_r ? k.col_r[u] == k.col_l[w] : k.col_l[u] == k.col_r[w];
 }
 
-__global__ __launch_bounds__(256) void k_filter(FilterArgs f, uint32_t *flag) {
+// Row of every CSR position of one side (one wave per row; once per call).
+__global__ __launch_bounds__(256) void k_row_of(const uint32_t *off, uint32_t n, uint32_t *row) {
     const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
-    for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < f.nl; u += gridDim.x * wpb) {
-        const uint32_t l = f.id_l[u];
-        for (uint32_t k = f.off_l[u] + lane; k < f.off_l[u + 1]; k += WAVE)
-            flag[k] = keep_edge(f, l, f.id_r[f.adj_l[k]]);
+    for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < n; u += gridDim.x * wpb)
+        for (uint32_t p = off[u] + lane; p < off[u + 1]; p += WAVE) row[p] = u;
+}
+
+// Keep flag of every CSR position of one side, one thread per position.
+__global__ __launch_bounds__(256) void k_keep_flags(SideView v, KeepRule k, const uint32_t *row,
+                                                    uint64_t m, uint32_t *flag) {
+    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < m;
+         p += (uint64_t)gridDim.x * blockDim.x)
+        flag[p] = keep_edge(k, v, row[p], v.adj[p]);
+}
+
+// Kept entries of row u, from the inclusive scan of the keep flags.
+__device__ inline uint32_t kept_in_row(const uint32_t *off, const uint32_t *scan, uint32_t u) {
+    const uint32_t rb = off[u], re = off[u + 1];
+    return (re ? scan[re - 1] : 0u) - (rb ? scan[rb - 1] : 0u);
+}
+
+// mark[u] = 1 when row u keeps an edge.
+__global__ void k_kept_marks(const uint32_t *off, uint32_t n, const uint32_t *scan,
+                             uint32_t *mark) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < n;
+         u += (uint64_t)gridDim.x * blockDim.x)
+        mark[u] = kept_in_row(off, scan, (uint32_t)u) != 0u;
+}
+
+// out[0] += rows that keep an edge, out[1] += sum of squared kept degrees.
+__global__ __launch_bounds__(256) void k_kept_stats(const uint32_t *off, uint32_t n,
+                                                    const uint32_t *scan,
+                                                    unsigned long long *out) {
+    __shared__ unsigned long long red[256 / WAVE];
+    unsigned long long c = 0, q = 0;
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < n;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long d = kept_in_row(off, scan, (uint32_t)u);
+        c += d != 0;
+        q += d * d;
+    }
+    c = block_sum64<256>(c, red);
+    q = block_sum64<256>(q, red);
+    if (threadIdx.x == 0) {
+        if (c) atomicAdd(&out[0], c);
+        if (q) atomicAdd(&out[1], q);
     }
 }
 
-// Kept edges, compacted by the inclusive scan of the flags (same row walk);
-// at most `cap` of them are written.
-__global__ __launch_bounds__(256) void k_compact(FilterArgs f, const uint32_t *scan1,
-                                                 uint32_t *kl, uint32_t *kr, uint32_t cap) {
-    const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
-    for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < f.nl; u += gridDim.x * wpb) {
-        const uint32_t l = f.id_l[u];
-        for (uint32_t k = f.off_l[u] + lane; k < f.off_l[u + 1]; k += WAVE) {
-            const uint32_t prev = k ? scan1[k - 1] : 0;
-            if (scan1[k] != prev && prev < cap) {
-                kl[prev] = l;
-                kr[prev] = f.id_r[f.adj_l[k]];
-            }
+// One side's kept rows written into a CSR (one part of a union, or the whole
+// kept graph): the row of new rank r at out_off[vbase + r], its entries at
+// ebase + their kept index, each the neighbour's new rank plus vbase_o and,
+// when out_xpos is given, the position of the same edge in the other side's
+// output.  Nothing is written once *bad is set (a part whose sizes differ
+// from those its buffers were sized for).  Offsets one thread per row,
+// entries one thread per position.
+struct EmitArgs {
+    const uint32_t *off, *adj, *xpos;   // source side
+    const uint32_t *scan, *scan_o;      // keep-flag scans: this side's order, the other side's
+    const uint32_t *vscan, *vscan_o;    // kept-vertex mark scans: this side, the other side
+    uint32_t n;
+    uint64_t ebase;
+    uint32_t vbase, vbase_o;
+    uint32_t *out_off, *out_adj, *out_xpos;
+    const uint32_t *bad;
+};
+
+__global__ __launch_bounds__(256) void k_emit_offsets(EmitArgs a) {
+    if (a.bad && *a.bad) return;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = (uint32_t)i;
+        const uint32_t rb = a.off[u], re = a.off[u + 1];
+        const uint32_t s0 = rb ? a.scan[rb - 1] : 0u;
+        const uint32_t s1 = re ? a.scan[re - 1] : 0u;
+        if (s1 != s0) a.out_off[a.vbase + a.vscan[u] - 1] = (uint32_t)(a.ebase + s0);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emit_entries(EmitArgs a, uint64_t m) {
+    if (a.bad && *a.bad) return;
+    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < m;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t inc = a.scan[p], prev = p ? a.scan[p - 1] : 0u;
+        if (inc != prev) {
+            const uint64_t q = a.ebase + prev;
+            a.out_adj[q] = a.vbase_o + a.vscan_o[a.adj[p]] - 1u;
+            if (a.out_xpos) a.out_xpos[q] = (uint32_t)(a.ebase + a.scan_o[a.xpos[p]] - 1u);
         }
     }
 }
 
-__global__ void k_colours(uint32_t n, uint32_t side, uint32_t N, uint64_t seed, uint32_t *col) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * blockDim.x)
-        col[v] = colour_of(seed, side, v, N);
+// Tail of a kept graph laid out on the graph's own sizes (the single
+// sparsifier calls, whose kept sizes stay on the device): rows from the kept
+// vertex count to n end at the kept edge count, and adjacency positions from
+// the kept edge count to m hold a rank no vertex has, so the count's
+// planning starts a segment there.
+__global__ void k_kept_tail(uint32_t *off, uint32_t n, const uint32_t *vscan,
+                            const uint32_t *escan, uint64_t m, uint32_t *adj) {
+    const uint32_t nk = n ? vscan[n - 1] : 0u;
+    const uint32_t mk = m ? escan[m - 1] : 0u;
+    const uint64_t lim = (uint64_t)n + 1 > m ? (uint64_t)n + 1 : m;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < lim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i <= n && i >= nk) off[i] = mk;
+        if (i < m && i >= mk) adj[i] = 0xFFFFFFFFu;
+    }
+}
+
+__global__ void k_kept_total(const uint32_t *escan, uint64_t m, unsigned long long *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = m ? escan[m - 1] : 0u;
+}
+
+// ClrSpar colours of one side by rank (the colour is drawn for the id).
+__global__ void k_colours(uint32_t n, uint32_t side, uint32_t N, uint64_t seed,
+                          const uint32_t *id, uint32_t *col) {
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n;
+         r += (uint64_t)gridDim.x * blockDim.x)
+        col[r] = colour_of(seed, side, id[r], N);
 }
 
 __global__ void k_est_scale(const unsigned long long *beta, double scale_div, double scale_mul,
@@ -163,21 +271,39 @@ __global__ void k_prob_scan(const double *probs, uint64_t n, ProbFlags *f) {
     if (mx) atomicMax(&f->max_bits, mx);
 }
 
+// Probabilities that fail the check (negative, NaN, infinite, all zero) are
+// replaced by equal weights, so the draws that follow stay well defined; the
+// estimate is then NaN (probs_ok below).
+__device__ inline bool probs_ok(const ProbFlags *f) { return !f->bad && f->max_bits != 0; }
+
+// Integer weights into w and pre (pre is then scanned in place).
 __global__ void k_quantise(const double *probs, uint64_t n, const ProbFlags *f,
-                           unsigned long long *w) {
+                           unsigned long long *w, unsigned long long *pre) {
+    const bool ok = probs_ok(f);
     const double mx = __longlong_as_double((long long)f->max_bits);
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const double p = probs[i];
-        unsigned long long q = 0;
-        if (p > 0.0) {
+        unsigned long long q = ok ? 0 : 1;
+        if (ok && p > 0.0) {
             const double s = floor(p / mx * 4294967295.0);
             const uint32_t v = (uint32_t)s;
             q = v < 1 ? 1 : v;
         }
         w[i] = q;
+        pre[i] = q;
     }
 }
+
+__global__ void k_zero_flags(ProbFlags *f) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        f->max_bits = 0;
+        f->bad = 0;
+        f->overflow = 0;
+    }
+}
+
+__device__ inline double nan64() { return __longlong_as_double(0x7FF8000000000000ll); }
 
 // Inclusive prefix sum of uint64 (same reduce-then-scan as the uint32 scan).
 constexpr int S64_NT = 256, S64_PER = 8, S64_TILE = S64_NT * S64_PER;
@@ -293,6 +419,19 @@ __global__ void k_gather_vertex(uint64_t k, const uint32_t *ids, uint32_t nl,
     }
 }
 
+// The draws alone: drawn global ids, each draw's integer weight (1 when
+// uniform) and the weight total.
+__global__ void k_draw_ids(uint64_t k, uint64_t n, const unsigned long long *draw,
+                           const uint32_t *wdraw, const unsigned long long *pre, uint32_t *ids,
+                           uint32_t *weights, unsigned long long *total) {
+    const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    for (uint64_t i = t0; i < k; i += (uint64_t)gridDim.x * blockDim.x) {
+        ids[i] = (uint32_t)draw[i];
+        if (weights) weights[i] = pre ? wdraw[i] : 1u;
+    }
+    if (total && t0 == 0) *total = pre ? pre[n - 1] : n;
+}
+
 // ESamp: A-side CSR position of every edge, then mark the drawn edges' starts.
 __global__ void k_pos_of_edge(const uint32_t *eidA, uint64_t m, uint32_t *pos) {
     for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < m;
@@ -336,6 +475,10 @@ __global__ __launch_bounds__(256) void k_combine(uint64_t k, uint64_t n,
     if (threadIdx.x == 0) ovf = 0;
     __syncthreads();
     const uint64_t nb = (k + COMBINE_BLOCK - 1) / COMBINE_BLOCK;
+    if (pre && !probs_ok(f)) {
+        if (threadIdx.x == 0) *est = nan64();
+        return;
+    }
     if (pre) {
         const double Q = (double)pre[n - 1];
         for (uint64_t b = threadIdx.x; b < nb; b += blockDim.x) {
@@ -368,7 +511,7 @@ __global__ __launch_bounds__(256) void k_combine(uint64_t k, uint64_t n,
                 if (t + c < t) ovf = 1;
                 t += c;
             }
-            *est = ((double)t * (double)n) / (4.0 * (double)k);
+            *est = ovf ? nan64() : ((double)t * (double)n) / (4.0 * (double)k);
             if (ovf) f->overflow = 1;
         }
     }
@@ -510,12 +653,13 @@ __global__ void k_block_sums(const double *terms, uint64_t k, double *parts) {
     }
 }
 
-__global__ void k_fast_total(uint64_t k, uint32_t alpha, const double *parts, double *est) {
+__global__ void k_fast_total(uint64_t k, uint32_t alpha, const double *parts, const ProbFlags *f,
+                             double *est) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const uint64_t nb = (k + COMBINE_BLOCK - 1) / COMBINE_BLOCK;
         double total = 0.0;
         for (uint64_t b = 0; b < nb; b++) total += parts[b];
-        *est = total / ((double)k * (double)alpha);
+        *est = (f && !probs_ok(f)) ? nan64() : total / ((double)k * (double)alpha);
     }
 }
 
@@ -713,55 +857,176 @@ static inline unsigned grid_for(uint64_t n, int nt = 256) {
 }
 
 // ------------------------------------------------------------------ host: sparsifiers
-struct SparWs {
-    uint32_t *flag, *scan_tmp, *kl, *kr, *col_l, *col_r;
-    void *storage;
-    size_t storage_bytes;
-    void *work;                 // graph build workspace, then the exact count's
-    size_t work_bytes;
-};
+static inline unsigned rows_grid(uint32_t n) {
+    unsigned g = grid_for(n, 4);
+    return g > 8192 ? 8192 : g;
+}
 
-static int carve_spar(Carver &c, uint32_t nl, uint32_t nr, uint64_t m, SparWs &w) {
-    size_t sb, bb;
-    BFC_TRY(bfc_graph_storage_size(nl, nr, m, &sb));
-    BFC_TRY(bfc_graph_build_ws_size(nl, nr, m, &bb));
-    const size_t eb = exact_ws_bound(nl, nr, m);
-    w.flag = c.take<uint32_t>(pad64(m));
-    w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(m));
-    w.kl = c.take<uint32_t>(pad64(m));
-    w.kr = c.take<uint32_t>(pad64(m));
-    w.col_l = c.take<uint32_t>(pad64(nl));
-    w.col_r = c.take<uint32_t>(pad64(nr));
-    w.storage_bytes = sb;
-    w.storage = c.take<char>(sb);
-    w.work_bytes = bb > eb ? bb : eb;
-    w.work = c.take<char>(w.work_bytes);
+static void side_views(const bfc_graph *g, SideView &L, SideView &R) {
+    L = SideView{g->off_l, g->adj_l, g->xpos_l, g->id_l, g->id_r, g->n_left, 0};
+    R = SideView{g->off_r, g->adj_r, g->xpos_r, g->id_r, g->id_l, g->n_right, 1};
+}
+
+static KeepRule espar_rule(double p, uint64_t seed) {
+    KeepRule k = {};
+    k.kind = 0;
+    k.seed = seed;
+    k.keep_all = p >= 1.0;
+    k.thresh = k.keep_all ? 0 : (uint64_t)ldexp(p, 64);
+    return k;
+}
+
+// ClrSpar's rule; the colours of both sides go to col_l / col_r.
+static int clrspar_rule(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint32_t *col_l,
+                        uint32_t *col_r, KeepRule &k, hipStream_t s) {
+    k = KeepRule{};
+    k.kind = 1;
+    k.seed = seed;
+    k.keep_all = ncolors == 1;
+    k.col_l = col_l;
+    k.col_r = col_r;
+    if (!k.keep_all) {
+        if (g->n_left)
+            k_colours<<<grid_for(g->n_left), 256, 0, s>>>(g->n_left, 0, ncolors, seed, g->id_l,
+                                                          col_l);
+        if (g->n_right)
+            k_colours<<<grid_for(g->n_right), 256, 0, s>>>(g->n_right, 1, ncolors, seed, g->id_r,
+                                                           col_r);
+        BFC_HIP(hipGetLastError());
+    }
     return BFC_OK;
 }
 
-// Filter, compact, rebuild and count the kept graph.
-static int sparsify_count(const bfc_graph *g, FilterArgs f, SparWs &w, uint64_t *d_beta,
-                          uint64_t *kept, hipStream_t s) {
-    const uint64_t m = g->n_edges;
-    uint64_t mk = 0;
-    if (m) {
-        unsigned gr = grid_for(g->n_left, 4);
-        if (gr > 8192) gr = 8192;
-        k_filter<<<gr, 256, 0, s>>>(f, w.flag);
-        BFC_HIP(hipGetLastError());
-        BFC_TRY(scan_u32_inclusive(w.flag, w.flag, m, w.scan_tmp, s));
-        k_compact<<<gr, 256, 0, s>>>(f, w.flag, w.kl, w.kr, 0xFFFFFFFFu);
-        BFC_HIP(hipGetLastError());
-        uint32_t last = 0;
-        BFC_HIP(hipMemcpyAsync(&last, w.flag + (m - 1), 4, hipMemcpyDeviceToHost, s));
-        BFC_HIP(hipStreamSynchronize(s));
-        mk = last;
+static int rule_of(const bfc_graph *g, const bfc_replica &r, uint32_t *col_l, uint32_t *col_r,
+                   KeepRule &k, hipStream_t s) {
+    if (r.kind == BFC_REPLICA_ESPAR) {
+        k = espar_rule(r.p, r.seed);
+        return BFC_OK;
     }
-    if (kept) *kept = mk;
-    bfc_graph h;
-    BFC_TRY(bfc_graph_build(g->n_left, g->n_right, mk, w.kl, w.kr, w.storage, w.storage_bytes,
-                            w.work, w.work_bytes, s, &h));
-    return bfc_exact(&h, BFC_SIDE_AUTO, d_beta, w.work, w.work_bytes, s);
+    return clrspar_rule(g, r.ncolors, r.seed, col_l, col_r, k, s);
+}
+
+// Buffers of one replica's keep flags: flags in both CSR orders (scanned in
+// place), kept-vertex marks of both sides (scanned in place), colours, and
+// the row of every CSR position (filled once per call by keep_rows).
+struct KeepWs {
+    uint32_t *fl, *fr, *ml, *mr, *scan_tmp, *col_l, *col_r, *row_l, *row_r;
+};
+
+static void carve_keep(Carver &c, const bfc_graph *g, KeepWs &w) {
+    const uint64_t m = g->n_edges;
+    uint64_t big = m;
+    if (g->n_left > big) big = g->n_left;
+    if (g->n_right > big) big = g->n_right;
+    w.fl = c.take<uint32_t>(pad64(m));
+    w.fr = c.take<uint32_t>(pad64(m));
+    w.ml = c.take<uint32_t>(pad64(g->n_left));
+    w.mr = c.take<uint32_t>(pad64(g->n_right));
+    w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(big));
+    w.col_l = c.take<uint32_t>(pad64(g->n_left));
+    w.col_r = c.take<uint32_t>(pad64(g->n_right));
+    w.row_l = c.take<uint32_t>(pad64(m));
+    w.row_r = c.take<uint32_t>(pad64(m));
+}
+
+static int keep_rows(const bfc_graph *g, KeepWs &w, hipStream_t s) {
+    if (!g->n_edges) return BFC_OK;
+    k_row_of<<<rows_grid(g->n_left), 256, 0, s>>>(g->off_l, g->n_left, w.row_l);
+    k_row_of<<<rows_grid(g->n_right), 256, 0, s>>>(g->off_r, g->n_right, w.row_r);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+// Offsets and entries of one side's kept rows (EmitArgs above).
+static int emit(const EmitArgs &a, uint64_t m, hipStream_t s) {
+    k_emit_offsets<<<grid_for(a.n), 256, 0, s>>>(a);
+    k_emit_entries<<<grid_for(m), 256, 0, s>>>(a, m);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
+}
+
+// Keep flags of both CSR orders and their inclusive scans; with `marks`,
+// the kept-vertex marks of both sides and their inclusive scans too.
+static int keep_and_scan(const bfc_graph *g, const KeepRule &k, KeepWs &w, bool marks,
+                         hipStream_t s) {
+    SideView L, R;
+    side_views(g, L, R);
+    const uint64_t m = g->n_edges;
+    if (m) {
+        k_keep_flags<<<grid_for(m), 256, 0, s>>>(L, k, w.row_l, m, w.fl);
+        k_keep_flags<<<grid_for(m), 256, 0, s>>>(R, k, w.row_r, m, w.fr);
+        BFC_HIP(hipGetLastError());
+        BFC_TRY(scan_u32_inclusive(w.fl, w.fl, m, w.scan_tmp, s));
+        BFC_TRY(scan_u32_inclusive(w.fr, w.fr, m, w.scan_tmp, s));
+    }
+    if (marks) {
+        if (g->n_left) {
+            k_kept_marks<<<grid_for(g->n_left), 256, 0, s>>>(g->off_l, g->n_left, w.fl, w.ml);
+            BFC_TRY(scan_u32_inclusive(w.ml, w.ml, g->n_left, w.scan_tmp, s));
+        }
+        if (g->n_right) {
+            k_kept_marks<<<grid_for(g->n_right), 256, 0, s>>>(g->off_r, g->n_right, w.fr, w.mr);
+            BFC_TRY(scan_u32_inclusive(w.mr, w.mr, g->n_right, w.scan_tmp, s));
+        }
+        BFC_HIP(hipGetLastError());
+    }
+    return BFC_OK;
+}
+
+// The single sparsifier calls: the kept graph laid out on the graph's own
+// sizes (rows beyond the kept vertices empty), counted from the side
+// ExactBFC's rule picks for the graph itself.  The count is the same from
+// either side; the kept sizes never leave the device, so the call is
+// asynchronous.
+struct SparWs {
+    KeepWs k;
+    uint32_t *off_l, *adj_l, *off_r, *adj_r, *xpos;
+    void *work;                 // the exact count's workspace
+    size_t work_bytes;
+};
+
+static void carve_spar(Carver &c, const bfc_graph *g, SparWs &w) {
+    carve_keep(c, g, w.k);
+    const uint64_t m = g->n_edges;
+    w.off_l = c.take<uint32_t>(pad64((uint64_t)g->n_left + 1));
+    w.off_r = c.take<uint32_t>(pad64((uint64_t)g->n_right + 1));
+    w.adj_l = c.take<uint32_t>(pad64(m + ADJ_SLACK));
+    w.adj_r = c.take<uint32_t>(pad64(m + ADJ_SLACK));
+    w.xpos = c.take<uint32_t>(pad64(m));
+    w.work_bytes = exact_ws_bound(g->n_left, g->n_right, m);
+    w.work = c.take<char>(w.work_bytes);
+}
+
+static int sparsify_count(const bfc_graph *g, const KeepRule &k, SparWs &w, uint64_t *d_beta,
+                          uint64_t *d_kept, hipStream_t s) {
+    const uint64_t m = g->n_edges;
+    const uint32_t nl = g->n_left, nr = g->n_right;
+    BFC_TRY(keep_rows(g, w.k, s));
+    BFC_TRY(keep_and_scan(g, k, w.k, true, s));
+    const int side = bfc_side_used(g, BFC_SIDE_AUTO);
+    if (side < 0) return side;
+    const bool from_r = side == BFC_SIDE_R;
+    if (m) {
+        EmitArgs el = {g->off_l, g->adj_l, g->xpos_l, w.k.fl, w.k.fr, w.k.ml, w.k.mr, nl,
+                       0, 0, 0, w.off_l, w.adj_l, from_r ? nullptr : w.xpos, nullptr};
+        EmitArgs er = {g->off_r, g->adj_r, g->xpos_r, w.k.fr, w.k.fl, w.k.mr, w.k.ml, nr,
+                       0, 0, 0, w.off_r, w.adj_r, from_r ? w.xpos : nullptr, nullptr};
+        BFC_TRY(emit(el, m, s));
+        BFC_TRY(emit(er, m, s));
+    }
+    k_kept_tail<<<grid_for(m > nl ? m : (uint64_t)nl + 1), 256, 0, s>>>(w.off_l, nl, w.k.ml,
+                                                                        w.k.fl, m, w.adj_l);
+    k_kept_tail<<<grid_for(m > nr ? m : (uint64_t)nr + 1), 256, 0, s>>>(w.off_r, nr, w.k.mr,
+                                                                        w.k.fr, m, w.adj_r);
+    if (d_kept) k_kept_total<<<1, 64, 0, s>>>(w.k.fl, m, (unsigned long long *)d_kept);
+    BFC_HIP(hipGetLastError());
+    // the kept graph: the graph's sizes and statistics as upper bounds
+    bfc_graph h = *g;
+    h.off_l = w.off_l; h.adj_l = w.adj_l; h.off_r = w.off_r; h.adj_r = w.adj_r;
+    h.xpos_l = from_r ? nullptr : w.xpos;
+    h.xpos_r = from_r ? w.xpos : nullptr;
+    h.eid_l = h.eid_r = h.rank_l = h.rank_r = h.id_l = h.id_r = nullptr;
+    return bfc_exact(&h, side, d_beta, w.work, w.work_bytes, s);
 }
 
 }  // namespace bfc
@@ -774,56 +1039,45 @@ int bfc_spar_ws_size(const bfc_graph *g, size_t *bytes) {
     if (!g || !bytes) return BFC_E_NULL;
     Carver c(nullptr, 0);
     SparWs w;
-    BFC_TRY(carve_spar(c, g->n_left, g->n_right, g->n_edges, w));
+    carve_spar(c, g, w);
     *bytes = c.used;
     return BFC_OK;
 }
 
-int bfc_espar(const bfc_graph *g, double p, uint64_t seed, uint64_t *d_beta, double *d_est,
-              uint64_t *kept_edges, void *d_ws, size_t ws_bytes, hipStream_t s) {
+static int spar_args(const bfc_graph *g, uint64_t *d_beta, double *d_est, uint64_t *d_kept,
+                     void *d_ws) {
     if (!g || !d_beta || !d_est || !d_ws) return BFC_E_NULL;
+    if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7) ||
+        ((uintptr_t)d_kept & 7))
+        return BFC_E_ALIGN;
+    return BFC_OK;
+}
+
+int bfc_espar(const bfc_graph *g, double p, uint64_t seed, uint64_t *d_beta, double *d_est,
+              uint64_t *d_kept, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    BFC_TRY(spar_args(g, d_beta, d_est, d_kept, d_ws));
     if (!(p > 0.0) || !(p <= 1.0)) return BFC_E_ARG;
-    if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
     Carver c(d_ws, ws_bytes);
     SparWs w;
-    BFC_TRY(carve_spar(c, g->n_left, g->n_right, g->n_edges, w));
+    carve_spar(c, g, w);
     if (!c.fits()) return BFC_E_WS_SMALL;
-    FilterArgs f = {};
-    f.off_l = g->off_l; f.adj_l = g->adj_l; f.id_l = g->id_l; f.id_r = g->id_r;
-    f.nl = g->n_left;
-    f.kind = 0;
-    f.seed = seed;
-    f.keep_all = p >= 1.0;
-    f.thresh = f.keep_all ? 0 : (uint64_t)ldexp(p, 64);
-    BFC_TRY(sparsify_count(g, f, w, d_beta, kept_edges, s));
+    BFC_TRY(sparsify_count(g, espar_rule(p, seed), w, d_beta, d_kept, s));
     k_est_scale<<<1, 64, 0, s>>>((unsigned long long *)d_beta, (p * p) * (p * p), 0.0, d_est);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
 
 int bfc_clrspar(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint64_t *d_beta,
-                double *d_est, uint64_t *kept_edges, void *d_ws, size_t ws_bytes, hipStream_t s) {
-    if (!g || !d_beta || !d_est || !d_ws) return BFC_E_NULL;
+                double *d_est, uint64_t *d_kept, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    BFC_TRY(spar_args(g, d_beta, d_est, d_kept, d_ws));
     if (ncolors == 0) return BFC_E_ARG;
-    if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
     Carver c(d_ws, ws_bytes);
     SparWs w;
-    BFC_TRY(carve_spar(c, g->n_left, g->n_right, g->n_edges, w));
+    carve_spar(c, g, w);
     if (!c.fits()) return BFC_E_WS_SMALL;
-    FilterArgs f = {};
-    f.off_l = g->off_l; f.adj_l = g->adj_l; f.id_l = g->id_l; f.id_r = g->id_r;
-    f.nl = g->n_left;
-    f.kind = 1;
-    f.seed = seed;
-    f.keep_all = ncolors == 1;
-    f.col_l = w.col_l;
-    f.col_r = w.col_r;
-    if (!f.keep_all) {
-        if (g->n_left) k_colours<<<grid_for(g->n_left), 256, 0, s>>>(g->n_left, 0, ncolors, seed, w.col_l);
-        if (g->n_right) k_colours<<<grid_for(g->n_right), 256, 0, s>>>(g->n_right, 1, ncolors, seed, w.col_r);
-        BFC_HIP(hipGetLastError());
-    }
-    BFC_TRY(sparsify_count(g, f, w, d_beta, kept_edges, s));
+    KeepRule k;
+    BFC_TRY(clrspar_rule(g, ncolors, seed, w.k.col_l, w.k.col_r, k, s));
+    BFC_TRY(sparsify_count(g, k, w, d_beta, d_kept, s));
     const double N = (double)ncolors;
     k_est_scale<<<1, 64, 0, s>>>((unsigned long long *)d_beta, 0.0, N * N * N, d_est);
     BFC_HIP(hipGetLastError());
@@ -833,87 +1087,81 @@ int bfc_clrspar(const bfc_graph *g, uint32_t ncolors, uint64_t seed, uint64_t *d
 }  // extern "C"
 
 // ------------------------------------------------------------------ host: replica batches
-// Many ESpar / ClrSpar replicas of one graph counted in one launch: each
-// replica's kept edges are compacted into a shared pool with its vertices
-// renumbered densely (isolated vertices dropped: they carry no butterfly),
-// the replicas become the parts of one disjoint union (each oriented by
-// ExactBFC's side rule) and bfc_exact_parts counts them together.  Every
-// replica's count and estimate equal those of bfc_espar / bfc_clrspar with
-// the same parameters and seed.
+// Many ESpar / ClrSpar replicas of one graph counted together.  Phase 1
+// measures each replica's kept graph (edges, vertices keeping an edge, sums
+// of squared kept degrees).  Phase 2 builds every kept graph, oriented by
+// ExactBFC's rule on its own degrees, as one part of a disjoint union laid
+// out from those sizes (part i's union L ranks start at VL_i, its R ranks at
+// VR_i, its edges at E_i), and bfc_exact_parts counts all parts in one plan
+// and one launch per kernel class.  Phase 2 only launches kernels, so it can
+// be captured into a HIP graph and replayed.  Every replica's count and
+// estimate equal those of bfc_espar / bfc_clrspar with the same parameters
+// and seed.
 namespace bfc {
 
-__global__ void k_mark_ends(const uint32_t *kl, const uint32_t *kr, uint64_t mk, uint32_t *ml,
-                            uint32_t *mr) {
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < mk;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        ml[kl[e]] = 1u;
-        mr[kr[e]] = 1u;
+// Replica i's kept sizes against the ones phase 2 was laid out for.
+__global__ void k_check_part(const uint32_t *fl, uint64_t m, const uint32_t *ml, uint32_t nl,
+                             const uint32_t *mr, uint32_t nr, uint64_t kept, uint32_t kl,
+                             uint32_t kr, uint32_t *bad) {
+    if (threadIdx.x || blockIdx.x) return;
+    const uint64_t k = m ? fl[m - 1] : 0u;
+    const uint32_t a = nl ? ml[nl - 1] : 0u, b = nr ? mr[nr - 1] : 0u;
+    if (k != kept || a != kl || b != kr) atomicOr(bad, 1u);
+}
+
+// Per-part values: the part's first union L rank, the divisor / multiplier
+// of its estimate.
+__global__ void k_part_meta(uint32_t i, uint32_t vbase, double div, double mul, uint32_t *part_l,
+                            double *d_div, double *d_mul) {
+    if (threadIdx.x || blockIdx.x) return;
+    part_l[i] = vbase;
+    d_div[i] = div;
+    d_mul[i] = mul;
+}
+
+// Ends of the union's offset arrays.  A batch with a part that did not match
+// its sizes becomes a graph without edges (every row empty), so the count
+// reads only valid memory; its results are then marked as invalid.
+__global__ void k_union_finish(uint32_t *off_l, uint32_t nl, uint32_t *off_r, uint32_t nr,
+                               uint32_t M, uint32_t *part_l, uint32_t nparts, const uint32_t *bad) {
+    const bool b = *bad != 0u;
+    const uint64_t lim = (uint64_t)(nl > nr ? nl : nr) + 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < lim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i == 0) {
+            off_l[nl] = b ? 0u : M;
+            off_r[nr] = b ? 0u : M;
+            part_l[nparts] = nl;
+        }
+        if (b && i < nl) off_l[i] = 0u;
+        if (b && i < nr) off_r[i] = 0u;
     }
 }
 
-// New id = (inclusive scan of the marks at the old id) - 1.
-__global__ void k_renumber(uint32_t *kl, uint32_t *kr, uint64_t mk, const uint32_t *sl,
-                           const uint32_t *sr) {
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < mk;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        kl[e] = sl[kl[e]] - 1u;
-        kr[e] = sr[kr[e]] - 1u;
+// Estimates in the single-replica expressions; an invalid batch (sizes not
+// those of phase 1) gets counts 2^64 - 1 and NaN estimates.
+__global__ void k_est_batch(unsigned long long *beta, const double *div, const double *mul,
+                            uint32_t n, const uint32_t *bad, double *est) {
+    const bool b = *bad != 0u;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (b) {
+            beta[i] = ~0ull;
+            est[i] = __longlong_as_double(0x7FF8000000000000ll);
+            continue;
+        }
+        const double x = (double)beta[i];
+        est[i] = div[i] != 0.0 ? x / div[i] : x * mul[i];
     }
 }
 
-__global__ void k_store_last(const uint32_t *scan, uint64_t n, uint32_t *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *out = n ? scan[n - 1] : 0u;
-}
-
-__global__ void k_zero32(uint32_t *p, uint64_t n) {
+__global__ void k_zero_u32x(uint32_t *p, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
 }
 
-__global__ void k_est_batch(const unsigned long long *beta, const double *div, const double *mul,
-                            uint32_t n, double *est) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const double b = (double)beta[i];
-        est[i] = div[i] != 0.0 ? b / div[i] : b * mul[i];
-    }
-}
-
-// Degrees of the kept edges (flags from k_filter), by ids.
-__global__ __launch_bounds__(256) void k_kept_degrees(FilterArgs f, const uint32_t *flag,
-                                                      uint32_t *deg_l, uint32_t *deg_r) {
-    const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
-    for (uint32_t u = blockIdx.x * wpb + threadIdx.x / WAVE; u < f.nl; u += gridDim.x * wpb) {
-        const uint32_t l = f.id_l[u];
-        for (uint32_t k = f.off_l[u] + lane; k < f.off_l[u + 1]; k += WAVE)
-            if (flag[k]) {
-                atomicAdd(&deg_l[l], 1u);
-                atomicAdd(&deg_r[f.id_r[f.adj_l[k]]], 1u);
-            }
-    }
-}
-
-// out[0] += vertices of nonzero degree, out[1] += sum of squared degrees.
-__global__ __launch_bounds__(256) void k_deg_stats(const uint32_t *deg, uint64_t n,
-                                                   unsigned long long *out) {
-    __shared__ unsigned long long red[256 / WAVE];
-    unsigned long long c = 0, q = 0;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const unsigned long long d = deg[i];
-        c += d != 0;
-        q += d * d;
-    }
-    c = block_sum64<256>(c, red);
-    q = block_sum64<256>(q, red);
-    if (threadIdx.x == 0) {
-        if (c) atomicAdd(&out[0], c);
-        if (q) atomicAdd(&out[1], q);
-    }
-}
-
-__global__ void k_zero64(unsigned long long *p, uint64_t n) {
+__global__ void k_zero_u64x(unsigned long long *p, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = 0ull;
@@ -935,133 +1183,93 @@ static int check_replicas(uint32_t nrep, const bfc_replica *reps) {
     return BFC_OK;
 }
 
-struct FilterWs {
-    uint32_t *flag, *scan_tmp, *col_l, *col_r;
+// The union's layout from phase 1: part i starts from R (its sides
+// exchanged) when its sum of squared kept L degrees is below its R one.
+struct UnionLayout {
+    std::vector<uint64_t> ebase;
+    std::vector<uint32_t> vl, vr;       // first union L / R rank of each part
+    std::vector<uint8_t> swapped;
+    uint64_t M, NL, NR, wedges;         // wedges: sum over union R vertices of C(d, 2)
 };
 
-static void carve_filter(Carver &c, const bfc_graph *g, FilterWs &w) {
-    w.flag = c.take<uint32_t>(pad64(g->n_edges));
-    w.scan_tmp = c.take<uint32_t>(scan_tmp_elems(g->n_edges));
-    w.col_l = c.take<uint32_t>(pad64(g->n_left));
-    w.col_r = c.take<uint32_t>(pad64(g->n_right));
-}
-
-// Keep flags of replica `rep` in w.flag, then their inclusive scan.
-static int filter_replica(const bfc_graph *g, const bfc_replica &rep, FilterWs &w,
-                          FilterArgs &f, hipStream_t s) {
-    f = FilterArgs{};
-    f.off_l = g->off_l; f.adj_l = g->adj_l; f.id_l = g->id_l; f.id_r = g->id_r;
-    f.nl = g->n_left;
-    f.seed = rep.seed;
-    if (rep.kind == BFC_REPLICA_ESPAR) {
-        f.kind = 0;
-        f.keep_all = rep.p >= 1.0;
-        f.thresh = f.keep_all ? 0 : (uint64_t)ldexp(rep.p, 64);
-    } else {
-        f.kind = 1;
-        f.keep_all = rep.ncolors == 1;
-        f.col_l = w.col_l;
-        f.col_r = w.col_r;
-        if (!f.keep_all) {
-            if (g->n_left)
-                k_colours<<<grid_for(g->n_left), 256, 0, s>>>(g->n_left, 0, rep.ncolors, rep.seed,
-                                                              w.col_l);
-            if (g->n_right)
-                k_colours<<<grid_for(g->n_right), 256, 0, s>>>(g->n_right, 1, rep.ncolors,
-                                                               rep.seed, w.col_r);
-        }
-    }
-    const uint64_t m = g->n_edges;
-    if (m) {
-        unsigned gr = grid_for(g->n_left, 4);
-        if (gr > 8192) gr = 8192;
-        k_filter<<<gr, 256, 0, s>>>(f, w.flag);
-        BFC_HIP(hipGetLastError());
-        BFC_TRY(scan_u32_inclusive(w.flag, w.flag, m, w.scan_tmp, s));
-    }
-    BFC_HIP(hipGetLastError());
-    return BFC_OK;
-}
-
-struct BatchWs {
-    FilterWs f;
-    uint32_t *ml, *mr, *scan_tmp_v, *kl, *kr, *kept_dev, *sizes_dev, *part_l, *part_r;
-    double *div, *mul;
-    void *storage;
-    size_t storage_bytes;
-    void *work;
-    size_t work_bytes;
-};
-
-// Sizes of the union: edges, vertices of each union side (each part enters
-// with its start side as L: ExactBFC's rule on its own degrees), and the
-// sums of the parts' vertex counts before orientation.
-struct BatchSizes {
-    uint64_t M, NL, NR, SL, SR;
-};
-
-static int batch_sizes(uint32_t nrep, const bfc_replica_info *info, BatchSizes &z) {
-    z = BatchSizes{0, 0, 0, 0, 0};
+static int union_layout(uint32_t nrep, const bfc_replica_info *info, UnionLayout &u) {
+    u.ebase.assign(nrep + 1, 0);
+    u.vl.assign(nrep + 1, 0);
+    u.vr.assign(nrep + 1, 0);
+    u.swapped.assign(nrep, 0);
+    uint64_t M = 0, NL = 0, NR = 0, W = 0;
     for (uint32_t i = 0; i < nrep; i++) {
         const bfc_replica_info &r = info[i];
         const bool sw = r.sumsq_left < r.sumsq_right;
-        z.M += r.kept;
-        z.NL += sw ? r.n_right : r.n_left;
-        z.NR += sw ? r.n_left : r.n_right;
-        z.SL += r.n_left;
-        z.SR += r.n_right;
+        u.swapped[i] = sw;
+        u.ebase[i] = M;
+        u.vl[i] = (uint32_t)NL;
+        u.vr[i] = (uint32_t)NR;
+        M += r.kept;
+        NL += sw ? r.n_right : r.n_left;
+        NR += sw ? r.n_left : r.n_right;
+        // midpoints are the part's other side: sum C(d,2) = (sum d^2 - sum d) / 2
+        const uint64_t sq = sw ? r.sumsq_left : r.sumsq_right;
+        if (sq < r.kept) return BFC_E_ARG;
+        W += (sq - r.kept) / 2;
+        if (M > 0xFFFFFFFFull - ADJ_SLACK || NL > 0xFFFFFFFEull || NR > 0xFFFFFFFEull)
+            return BFC_E_TOO_LARGE;
     }
-    if (z.M > 0xFFFFFFFFull - ADJ_SLACK || z.NL > 0xFFFFFFFEull || z.NR > 0xFFFFFFFEull)
-        return BFC_E_TOO_LARGE;
+    u.ebase[nrep] = M;
+    u.vl[nrep] = (uint32_t)NL;
+    u.vr[nrep] = (uint32_t)NR;
+    u.M = M;
+    u.NL = NL;
+    u.NR = NR;
+    u.wedges = W;
     return BFC_OK;
 }
 
+// The union as a bfc_graph (L = every part's start side).  Ranks are the
+// union's vertex numbers (rank_l left NULL: the identity for the per-part
+// sums); the largest degree of the graph bounds every kept degree.
+static bfc_graph union_graph(const bfc_graph *g, const UnionLayout &u, uint32_t *off_l,
+                             uint32_t *adj_l, uint32_t *xpos_l, uint32_t *off_r, uint32_t *adj_r) {
+    bfc_graph h = {};
+    h.n_left = (uint32_t)u.NL;
+    h.n_right = (uint32_t)u.NR;
+    h.n_edges = u.M;
+    h.off_l = off_l; h.adj_l = adj_l; h.xpos_l = xpos_l;
+    h.off_r = off_r; h.adj_r = adj_r;
+    const uint32_t md = g->max_deg_l > g->max_deg_r ? g->max_deg_l : g->max_deg_r;
+    h.max_deg_l = h.max_deg_r = md;
+    h.wedges_mid_r = u.wedges;
+    h.sumsq_l = 1;                       // the union is always counted from L
+    h.device = g->device;
+    return h;
+}
+
+struct BatchWs {
+    KeepWs k;
+    uint32_t *off_l, *adj_l, *xpos_l, *off_r, *adj_r, *part_l, *bad;
+    double *div, *mul;
+    void *work;                          // bfc_exact_parts on the union
+    size_t work_bytes;
+};
+
 static int carve_batch(Carver &c, const bfc_graph *g, uint32_t nrep, const bfc_replica_info *info,
-                       BatchWs &w) {
-    BatchSizes z;
-    BFC_TRY(batch_sizes(nrep, info, z));
-    const uint64_t M = z.M;
-    carve_filter(c, g, w.f);
-    const uint64_t nv = (uint64_t)g->n_left > g->n_right ? g->n_left : g->n_right;
-    w.ml = c.take<uint32_t>(pad64(g->n_left));
-    w.mr = c.take<uint32_t>(pad64(g->n_right));
-    w.scan_tmp_v = c.take<uint32_t>(scan_tmp_elems(nv));
-    w.kl = c.take<uint32_t>(pad64(M));
-    w.kr = c.take<uint32_t>(pad64(M));
-    w.kept_dev = c.take<uint32_t>(nrep);
-    w.sizes_dev = c.take<uint32_t>(2 * (uint64_t)nrep);
+                       BatchWs &w, UnionLayout &u) {
+    BFC_TRY(union_layout(nrep, info, u));
+    carve_keep(c, g, w.k);
+    w.off_l = c.take<uint32_t>(pad64(u.NL + 1));
+    w.off_r = c.take<uint32_t>(pad64(u.NR + 1));
+    w.adj_l = c.take<uint32_t>(pad64(u.M + ADJ_SLACK));
+    w.adj_r = c.take<uint32_t>(pad64(u.M + ADJ_SLACK));
+    w.xpos_l = c.take<uint32_t>(pad64(u.M));
     w.part_l = c.take<uint32_t>(nrep + 1);
-    w.part_r = c.take<uint32_t>(nrep + 1);
+    w.bad = c.take<uint32_t>(1);
     w.div = c.take<double>(nrep);
     w.mul = c.take<double>(nrep);
-    size_t sb, bb, ub, pb;
-    BFC_TRY(bfc_graph_storage_size((uint32_t)z.NL, (uint32_t)z.NR, M, &sb));
-    BFC_TRY(bfc_graph_build_ws_size((uint32_t)z.NL, (uint32_t)z.NR, M, &bb));
-    // union workspace: offsets per part plus degree slots for both sides
-    {
-        Carver u(nullptr, 0);
-        u.take<uint64_t>(3 * ((uint64_t)nrep + 1));
-        u.take<uint32_t>(pad64(z.SL));
-        u.take<uint32_t>(pad64(z.SR));
-        u.take<uint32_t>(3 * ((uint64_t)nrep + 1));
-        u.take<uint8_t>(nrep + 1);
-        u.take<unsigned long long>(2 * (uint64_t)nrep);
-        ub = u.used + 16 * 256;     // the union carves these in more, separately rounded pieces
-    }
-    {
-        // bfc_exact_parts on a graph of these sizes, counted from L
-        Carver e(nullptr, 0);
-        e.take<char>(exact_ws_bound((uint32_t)z.NL, (uint32_t)z.NR, M));
-        e.take<unsigned long long>(pad64(z.NL > z.NR ? z.NL : z.NR));
-        e.take<unsigned long long>(1);
-        pb = e.used;
-    }
-    w.storage_bytes = sb;
-    w.storage = c.take<char>(sb);
-    w.work_bytes = bb;
-    if (ub > w.work_bytes) w.work_bytes = ub;
-    if (pb > w.work_bytes) w.work_bytes = pb;
-    w.work = c.take<char>(w.work_bytes);
+    bfc_graph h = union_graph(g, u, nullptr, nullptr, nullptr, nullptr, nullptr);
+    size_t pb = 0;
+    BFC_TRY(bfc_exact_parts_ws_size(&h, &pb));
+    w.work_bytes = pb;
+    w.work = c.take<char>(pb);
     return BFC_OK;
 }
 
@@ -1072,10 +1280,8 @@ extern "C" {
 int bfc_spar_batch_filter_ws_size(const bfc_graph *g, uint32_t nrep, size_t *bytes) {
     if (!g || !bytes) return BFC_E_NULL;
     Carver c(nullptr, 0);
-    FilterWs w;
-    carve_filter(c, g, w);
-    c.take<uint32_t>(pad64(g->n_left));
-    c.take<uint32_t>(pad64(g->n_right));
+    KeepWs w;
+    carve_keep(c, g, w);
     c.take<unsigned long long>(5 * (uint64_t)nrep);
     *bytes = c.used;
     return BFC_OK;
@@ -1087,32 +1293,23 @@ int bfc_spar_batch_filter(const bfc_graph *g, uint32_t nrep, const bfc_replica *
     BFC_TRY(check_replicas(nrep, reps));
     if (!aligned256(d_ws)) return BFC_E_ALIGN;
     Carver c(d_ws, ws_bytes);
-    FilterWs w;
-    carve_filter(c, g, w);
-    uint32_t *deg_l = c.take<uint32_t>(pad64(g->n_left));
-    uint32_t *deg_r = c.take<uint32_t>(pad64(g->n_right));
+    KeepWs w;
+    carve_keep(c, g, w);
     unsigned long long *st = c.take<unsigned long long>(5 * (uint64_t)nrep);
     if (!c.fits()) return BFC_E_WS_SMALL;
-    k_zero64<<<grid_for(5 * (uint64_t)nrep), 256, 0, s>>>(st, 5 * (uint64_t)nrep);
-    unsigned gr = grid_for(g->n_left, 4);
-    if (gr > 8192) gr = 8192;
-    unsigned gl = grid_for(g->n_left), gR = grid_for(g->n_right);
+    k_zero_u64x<<<grid_for(5 * (uint64_t)nrep), 256, 0, s>>>(st, 5 * (uint64_t)nrep);
+    BFC_TRY(keep_rows(g, w, s));
+    unsigned gl = grid_for(g->n_left), gr = grid_for(g->n_right);
     if (gl > 4096) gl = 4096;
-    if (gR > 4096) gR = 4096;
+    if (gr > 4096) gr = 4096;
     for (uint32_t i = 0; i < nrep; i++) {
-        FilterArgs f;
-        BFC_TRY(filter_replica(g, reps[i], w, f, s));
+        KeepRule k;
+        BFC_TRY(rule_of(g, reps[i], w.col_l, w.col_r, k, s));
+        BFC_TRY(keep_and_scan(g, k, w, false, s));
         unsigned long long *o = st + 5 * (uint64_t)i;
-        k_store_last<<<1, 64, 0, s>>>(w.flag, g->n_edges, (uint32_t *)(o + 4));
-        // the scan left the flags as running counts: recompute the flags for the degrees
-        k_zero32<<<grid_for(g->n_left), 256, 0, s>>>(deg_l, g->n_left);
-        k_zero32<<<grid_for(g->n_right), 256, 0, s>>>(deg_r, g->n_right);
-        if (g->n_edges) {
-            k_filter<<<gr, 256, 0, s>>>(f, w.flag);
-            k_kept_degrees<<<gr, 256, 0, s>>>(f, w.flag, deg_l, deg_r);
-        }
-        if (g->n_left) k_deg_stats<<<gl, 256, 0, s>>>(deg_l, g->n_left, o);
-        if (g->n_right) k_deg_stats<<<gR, 256, 0, s>>>(deg_r, g->n_right, o + 2);
+        if (g->n_left) k_kept_stats<<<gl, 256, 0, s>>>(g->off_l, g->n_left, w.fl, o);
+        if (g->n_right) k_kept_stats<<<gr, 256, 0, s>>>(g->off_r, g->n_right, w.fr, o + 2);
+        k_kept_total<<<1, 64, 0, s>>>(w.fl, g->n_edges, o + 4);
         BFC_HIP(hipGetLastError());
     }
     std::vector<unsigned long long> h(5 * (size_t)nrep);
@@ -1120,7 +1317,7 @@ int bfc_spar_batch_filter(const bfc_graph *g, uint32_t nrep, const bfc_replica *
     BFC_HIP(hipStreamSynchronize(s));
     for (uint32_t i = 0; i < nrep; i++) {
         const unsigned long long *o = &h[5 * (size_t)i];
-        h_info[i].kept = (uint32_t)o[4];
+        h_info[i].kept = o[4];
         h_info[i].n_left = (uint32_t)o[0];
         h_info[i].sumsq_left = o[1];
         h_info[i].n_right = (uint32_t)o[2];
@@ -1135,7 +1332,8 @@ int bfc_spar_batch_ws_size(const bfc_graph *g, uint32_t nrep, const bfc_replica 
     BFC_TRY(check_replicas(nrep, reps));
     Carver c(nullptr, 0);
     BatchWs w;
-    BFC_TRY(carve_batch(c, g, nrep, h_info, w));
+    UnionLayout u;
+    BFC_TRY(carve_batch(c, g, nrep, h_info, w, u));
     *bytes = c.used;
     return BFC_OK;
 }
@@ -1148,83 +1346,53 @@ int bfc_spar_batch(const bfc_graph *g, uint32_t nrep, const bfc_replica *reps,
     if (!aligned256(d_ws) || ((uintptr_t)d_beta & 7) || ((uintptr_t)d_est & 7)) return BFC_E_ALIGN;
     Carver c(d_ws, ws_bytes);
     BatchWs w;
-    BFC_TRY(carve_batch(c, g, nrep, h_info, w));
+    UnionLayout u;
+    BFC_TRY(carve_batch(c, g, nrep, h_info, w, u));
     if (!c.fits()) return BFC_E_WS_SMALL;
-    std::vector<uint64_t> h_kept(nrep);
-    for (uint32_t i = 0; i < nrep; i++) h_kept[i] = h_info[i].kept;
-
-    // 1. kept edges of every replica into the pool, vertices renumbered densely
-    std::vector<uint64_t> eoff(nrep + 1, 0);
-    for (uint32_t i = 0; i < nrep; i++) eoff[i + 1] = eoff[i] + h_kept[i];
-    const unsigned gr = grid_for(g->n_left, 4) > 8192 ? 8192 : grid_for(g->n_left, 4);
+    k_zero_u32x<<<1, 64, 0, s>>>(w.bad, 1);
+    BFC_TRY(keep_rows(g, w.k, s));
+    const uint64_t m = g->n_edges;
+    const uint32_t nl = g->n_left, nr = g->n_right;
     for (uint32_t i = 0; i < nrep; i++) {
-        FilterArgs f;
-        BFC_TRY(filter_replica(g, reps[i], w.f, f, s));
-        uint32_t *kl = w.kl + eoff[i], *kr = w.kr + eoff[i];
-        const uint64_t mk = h_kept[i];
-        if (g->n_edges) {
-            k_compact<<<gr, 256, 0, s>>>(f, w.f.flag, kl, kr, (uint32_t)mk);
-            k_store_last<<<1, 64, 0, s>>>(w.f.flag, g->n_edges, w.kept_dev + i);
-        } else {
-            k_zero32<<<1, 64, 0, s>>>(w.kept_dev + i, 1);
+        const bfc_replica &rep = reps[i];
+        KeepRule k;
+        BFC_TRY(rule_of(g, rep, w.k.col_l, w.k.col_r, k, s));
+        BFC_TRY(keep_and_scan(g, k, w.k, true, s));
+        k_check_part<<<1, 64, 0, s>>>(w.k.fl, m, w.k.ml, nl, w.k.mr, nr, h_info[i].kept,
+                                      h_info[i].n_left, h_info[i].n_right, w.bad);
+        if (m) {
+            // part i: its start side's rows into the union L (with cross
+            // positions), the other side's into the union R
+            const bool sw = u.swapped[i];
+            EmitArgs el = {g->off_l, g->adj_l, g->xpos_l, w.k.fl, w.k.fr, w.k.ml, w.k.mr, nl,
+                           u.ebase[i], sw ? u.vr[i] : u.vl[i], sw ? u.vl[i] : u.vr[i],
+                           sw ? w.off_r : w.off_l, sw ? w.adj_r : w.adj_l,
+                           sw ? nullptr : w.xpos_l, w.bad};
+            EmitArgs er = {g->off_r, g->adj_r, g->xpos_r, w.k.fr, w.k.fl, w.k.mr, w.k.ml, nr,
+                           u.ebase[i], sw ? u.vl[i] : u.vr[i], sw ? u.vr[i] : u.vl[i],
+                           sw ? w.off_l : w.off_r, sw ? w.adj_l : w.adj_r,
+                           sw ? w.xpos_l : nullptr, w.bad};
+            BFC_TRY(emit(el, m, s));
+            BFC_TRY(emit(er, m, s));
         }
-        k_zero32<<<grid_for(g->n_left), 256, 0, s>>>(w.ml, g->n_left);
-        k_zero32<<<grid_for(g->n_right), 256, 0, s>>>(w.mr, g->n_right);
-        if (mk) k_mark_ends<<<grid_for(mk), 256, 0, s>>>(kl, kr, mk, w.ml, w.mr);
-        BFC_HIP(hipGetLastError());
-        if (g->n_left) BFC_TRY(scan_u32_inclusive(w.ml, w.ml, g->n_left, w.scan_tmp_v, s));
-        if (g->n_right) BFC_TRY(scan_u32_inclusive(w.mr, w.mr, g->n_right, w.scan_tmp_v, s));
-        if (mk) k_renumber<<<grid_for(mk), 256, 0, s>>>(kl, kr, mk, w.ml, w.mr);
-        k_store_last<<<1, 64, 0, s>>>(w.ml, g->n_left, w.sizes_dev + 2 * (uint64_t)i);
-        k_store_last<<<1, 64, 0, s>>>(w.mr, g->n_right, w.sizes_dev + 2 * (uint64_t)i + 1);
-        BFC_HIP(hipGetLastError());
-    }
-    std::vector<uint32_t> kept(nrep), sizes(2 * (size_t)nrep);
-    BFC_HIP(hipMemcpyAsync(kept.data(), w.kept_dev, nrep * 4, hipMemcpyDeviceToHost, s));
-    BFC_HIP(hipMemcpyAsync(sizes.data(), w.sizes_dev, sizes.size() * 4, hipMemcpyDeviceToHost, s));
-    BFC_HIP(hipStreamSynchronize(s));
-    for (uint32_t i = 0; i < nrep; i++)        // h_info must be this graph's phase 1
-        if (kept[i] != h_kept[i] || sizes[2 * (size_t)i] != h_info[i].n_left ||
-            sizes[2 * (size_t)i + 1] != h_info[i].n_right)
-            return BFC_E_ARG;
-
-    // 2. the union (parts oriented by ExactBFC's rule), its CSRs, one count
-    std::vector<uint32_t> nl(nrep), nr(nrep), part_l(nrep + 1), part_r(nrep + 1);
-    std::vector<uint8_t> swapped(nrep);
-    for (uint32_t i = 0; i < nrep; i++) {
-        nl[i] = sizes[2 * (size_t)i];
-        nr[i] = sizes[2 * (size_t)i + 1];
-    }
-    BFC_TRY(bfc_batch_union(nrep, nl.data(), nr.data(), eoff.data(), w.kl, w.kr, w.kl, w.kr,
-                            part_l.data(), part_r.data(), swapped.data(), w.work, w.work_bytes,
-                            s));
-    bfc_graph u;
-    BFC_HIP(hipMemcpyAsync(w.part_l, part_l.data(), (nrep + 1) * 4, hipMemcpyHostToDevice, s));
-    BFC_HIP(hipMemcpyAsync(w.part_r, part_r.data(), (nrep + 1) * 4, hipMemcpyHostToDevice, s));
-    BFC_TRY(bfc_graph_build_parts(part_l[nrep], part_r[nrep], eoff[nrep], w.kl, w.kr, nrep,
-                                  w.part_l, w.part_r, w.storage, w.storage_bytes, w.work,
-                                  w.work_bytes, s, &u));
-    BFC_TRY(bfc_exact_parts(&u, nrep, w.part_l, tuning, d_beta, w.work, w.work_bytes, s));
-
-    // 3. estimates, in the single-replica expressions
-    std::vector<double> div(nrep), mul(nrep);
-    for (uint32_t i = 0; i < nrep; i++) {
-        const bfc_replica &r = reps[i];
-        if (r.kind == BFC_REPLICA_ESPAR) {
-            div[i] = (r.p * r.p) * (r.p * r.p);
-            mul[i] = 0.0;
+        double div = 0.0, mul = 0.0;
+        if (rep.kind == BFC_REPLICA_ESPAR) {
+            div = (rep.p * rep.p) * (rep.p * rep.p);
         } else {
-            const double N = (double)r.ncolors;
-            div[i] = 0.0;
-            mul[i] = N * N * N;
+            const double N = (double)rep.ncolors;
+            mul = N * N * N;
         }
+        k_part_meta<<<1, 64, 0, s>>>(i, u.vl[i], div, mul, w.part_l, w.div, w.mul);
+        BFC_HIP(hipGetLastError());
     }
-    BFC_HIP(hipMemcpyAsync(w.div, div.data(), nrep * 8, hipMemcpyHostToDevice, s));
-    BFC_HIP(hipMemcpyAsync(w.mul, mul.data(), nrep * 8, hipMemcpyHostToDevice, s));
-    k_est_batch<<<grid_for(nrep), 256, 0, s>>>((const unsigned long long *)d_beta, w.div, w.mul,
-                                               nrep, d_est);
+    k_union_finish<<<grid_for((u.NL > u.NR ? u.NL : u.NR) + 1), 256, 0, s>>>(
+        w.off_l, (uint32_t)u.NL, w.off_r, (uint32_t)u.NR, (uint32_t)u.M, w.part_l, nrep, w.bad);
     BFC_HIP(hipGetLastError());
-    BFC_HIP(hipStreamSynchronize(s));
+    bfc_graph h = union_graph(g, u, w.off_l, w.adj_l, w.xpos_l, w.off_r, w.adj_r);
+    BFC_TRY(bfc_exact_parts(&h, nrep, w.part_l, tuning, d_beta, w.work, w.work_bytes, s));
+    k_est_batch<<<grid_for(nrep), 256, 0, s>>>((unsigned long long *)d_beta, w.div, w.mul, nrep,
+                                               w.bad, d_est);
+    BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
 
@@ -1274,6 +1442,17 @@ static int carve_samp(Carver &c, const bfc_graph *g, uint64_t n, uint64_t k, int
     return BFC_OK;
 }
 
+// The draw buffers of carve_samp alone (bfc_vsamp_draws).
+static void carve_draws(Carver &c, uint64_t n, uint64_t k, SampWs &w) {
+    w = SampWs{};
+    w.flags = c.take<ProbFlags>(1);
+    w.w = c.take<unsigned long long>(pad64(n));
+    w.pre = c.take<unsigned long long>(pad64(n));
+    w.scan_tmp = c.take<unsigned long long>((n + S64_TILE - 1) / S64_TILE + 64);
+    w.draw = c.take<unsigned long long>(pad64(k));
+    w.wdraw = c.take<uint32_t>(pad64(k));
+}
+
 // Fast-eBFC sampler: the draw buffers of carve_samp, the edge position map
 // and the per-draw endpoints.
 static void carve_fast(Carver &c, uint64_t m, uint64_t k, SampWs &w, uint32_t *&ea,
@@ -1300,20 +1479,16 @@ static void carve_wsamp(Carver &c, uint64_t n, unsigned long long *&pre,
     parts = c.take<unsigned long long>(256);
 }
 
-// Weights, prefix sums and k draws over n items; returns BFC_E_PROBS for
-// invalid probabilities (reads the check back: synchronises).
+// Weights, prefix sums and k draws over n items.  Asynchronous: invalid
+// probabilities are detected on the device (the estimate becomes NaN);
+// bfc_probs_check reports them to the host.
 static int sample_draws(const double *d_probs, uint64_t n, uint64_t k, uint64_t seed,
                         uint32_t tag, SampWs &w, hipStream_t s) {
-    BFC_HIP(hipMemsetAsync(w.flags, 0, sizeof(ProbFlags), s));
+    k_zero_flags<<<1, 64, 0, s>>>(w.flags);
     if (d_probs) {
         k_prob_scan<<<grid_for(n), 256, 0, s>>>(d_probs, n, w.flags);
-        ProbFlags hf;
-        BFC_HIP(hipMemcpyAsync(&hf, w.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
-        BFC_HIP(hipStreamSynchronize(s));
-        if (hf.bad || hf.max_bits == 0) return BFC_E_PROBS;
-        k_quantise<<<grid_for(n), 256, 0, s>>>(d_probs, n, w.flags, w.w);
-        BFC_HIP(hipMemcpyAsync(w.pre, w.w, n * sizeof(unsigned long long),
-                               hipMemcpyDeviceToDevice, s));
+        k_quantise<<<grid_for(n), 256, 0, s>>>(d_probs, n, w.flags, w.w, w.pre);
+        BFC_HIP(hipGetLastError());
         BFC_TRY(scan_u64_inclusive(w.pre, n, w.scan_tmp, s));
     }
     k_draw<<<grid_for(k), 256, 0, s>>>(k, n, seed, tag, d_probs ? w.pre : nullptr, w.w, w.draw,
@@ -1327,15 +1502,34 @@ static int finish_estimate(uint64_t k, uint64_t n, const unsigned long long *cou
     k_combine<<<1, 256, 0, s>>>(k, n, counts, w.wdraw, weighted ? w.pre : nullptr, w.parts,
                                 w.flags, d_est);
     BFC_HIP(hipGetLastError());
-    ProbFlags hf;
-    BFC_HIP(hipMemcpyAsync(&hf, w.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
-    BFC_HIP(hipStreamSynchronize(s));
-    return hf.overflow ? BFC_E_OVERFLOW_RISK : BFC_OK;
+    return BFC_OK;
 }
 
 }  // namespace bfc
 
 extern "C" {
+
+int bfc_probs_check_ws_size(size_t *bytes) {
+    if (!bytes) return BFC_E_NULL;
+    *bytes = 256;
+    return BFC_OK;
+}
+
+int bfc_probs_check(const double *d_probs, uint64_t n, void *d_ws, size_t ws_bytes,
+                    hipStream_t s) {
+    if (!d_probs || !d_ws) return BFC_E_NULL;
+    if (n == 0) return BFC_E_ARG;
+    if (!aligned256(d_ws)) return BFC_E_ALIGN;
+    if (ws_bytes < sizeof(ProbFlags)) return BFC_E_WS_SMALL;
+    ProbFlags *f = (ProbFlags *)d_ws;
+    k_zero_flags<<<1, 64, 0, s>>>(f);
+    k_prob_scan<<<grid_for(n), 256, 0, s>>>(d_probs, n, f);
+    BFC_HIP(hipGetLastError());
+    ProbFlags hf;
+    BFC_HIP(hipMemcpyAsync(&hf, f, sizeof(hf), hipMemcpyDeviceToHost, s));
+    BFC_HIP(hipStreamSynchronize(s));
+    return (hf.bad || hf.max_bits == 0) ? BFC_E_PROBS : BFC_OK;
+}
 
 int bfc_vsamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
     if (!g || !bytes) return BFC_E_NULL;
@@ -1358,12 +1552,14 @@ int bfc_vsamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t se
     BFC_TRY(carve_samp(c, g, n, k, 0, w));
     if (!c.fits()) return BFC_E_WS_SMALL;
     BFC_TRY(sample_draws(d_probs, n, k, seed, TAG_VDRAW, w, s));
-    BFC_HIP(hipMemsetAsync(w.mark_l, 0, pad64(g->n_left), s));
-    BFC_HIP(hipMemsetAsync(w.mark_r, 0, pad64(g->n_right), s));
+    k_zero_u32x<<<grid_for(pad64(g->n_left) / 4), 256, 0, s>>>((uint32_t *)w.mark_l,
+                                                               pad64(g->n_left) / 4);
+    k_zero_u32x<<<grid_for(pad64(g->n_right) / 4), 256, 0, s>>>((uint32_t *)w.mark_r,
+                                                                pad64(g->n_right) / 4);
     k_mark_vertices<<<grid_for(k), 256, 0, s>>>(k, w.draw, g->n_left, g->rank_l, g->rank_r,
                                                 w.mark_l, w.mark_r, d_ids);
-    BFC_HIP(hipMemsetAsync(w.cnt_l, 0, pad64(g->n_left) * 8, s));
-    BFC_HIP(hipMemsetAsync(w.cnt_r, 0, pad64(g->n_right) * 8, s));
+    k_zero_u64x<<<grid_for(g->n_left), 256, 0, s>>>(w.cnt_l, g->n_left);
+    k_zero_u64x<<<grid_for(g->n_right), 256, 0, s>>>(w.cnt_r, g->n_right);
     BFC_HIP(hipGetLastError());
     // vBFC of every drawn vertex: the local walk from each side over the
     // marked starts only, per-vertex counts only
@@ -1377,6 +1573,35 @@ int bfc_vsamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t se
                                                 (unsigned long long *)d_counts);
     BFC_HIP(hipGetLastError());
     return finish_estimate(k, n, (unsigned long long *)d_counts, d_probs != nullptr, w, d_est, s);
+}
+
+int bfc_vsamp_draws_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
+    if (!g || !bytes) return BFC_E_NULL;
+    const uint64_t n = (uint64_t)g->n_left + g->n_right;
+    Carver c(nullptr, 0);
+    SampWs w;
+    carve_draws(c, n, k, w);
+    *bytes = c.used;
+    return BFC_OK;
+}
+
+int bfc_vsamp_draws(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t seed,
+                    uint32_t *d_ids, uint32_t *d_weights, uint64_t *d_total_weight, void *d_ws,
+                    size_t ws_bytes, hipStream_t s) {
+    if (!g || !d_ids || !d_ws) return BFC_E_NULL;
+    const uint64_t n = (uint64_t)g->n_left + g->n_right;
+    if (k == 0 || n == 0) return BFC_E_ARG;
+    if (!aligned256(d_ws) || ((uintptr_t)d_total_weight & 7)) return BFC_E_ALIGN;
+    Carver c(d_ws, ws_bytes);
+    SampWs w;
+    carve_draws(c, n, k, w);
+    if (!c.fits()) return BFC_E_WS_SMALL;
+    BFC_TRY(sample_draws(d_probs, n, k, seed, TAG_VDRAW, w, s));
+    k_draw_ids<<<grid_for(k), 256, 0, s>>>(k, n, w.draw, w.wdraw, d_probs ? w.pre : nullptr,
+                                           d_ids, d_weights,
+                                           (unsigned long long *)d_total_weight);
+    BFC_HIP(hipGetLastError());
+    return BFC_OK;
 }
 
 int bfc_esamp_ws_size(const bfc_graph *g, uint64_t k, size_t *bytes) {
@@ -1408,11 +1633,11 @@ int bfc_esamp(const bfc_graph *g, const double *d_probs, uint64_t k, uint64_t se
     const bool from_r = side == BFC_SIDE_R;
     const uint32_t nA = from_r ? g->n_right : g->n_left;
     uint8_t *mark = from_r ? w.mark_r : w.mark_l;
-    BFC_HIP(hipMemsetAsync(mark, 0, pad64(nA), s));
+    k_zero_u32x<<<grid_for(pad64(nA) / 4), 256, 0, s>>>((uint32_t *)mark, pad64(nA) / 4);
     k_pos_of_edge<<<grid_for(m), 256, 0, s>>>(from_r ? g->eid_r : g->eid_l, m, w.pos);
     k_mark_edges<<<grid_for(k), 256, 0, s>>>(k, w.draw, w.pos, from_r ? g->off_r : g->off_l, nA,
                                              mark);
-    BFC_HIP(hipMemsetAsync(w.cnt_e, 0, pad64(m) * 8, s));
+    k_zero_u64x<<<grid_for(m), 256, 0, s>>>(w.cnt_e, m);
     BFC_HIP(hipGetLastError());
     BFC_TRY(local_run(g, side, mark, nullptr, nullptr, (uint64_t *)w.cnt_e, w.local, w.local_bytes,
                       s));
@@ -1460,7 +1685,7 @@ int bfc_esamp_fast(const bfc_graph *g, const double *d_probs, uint64_t k, uint32
                                              terms);
     k_block_sums<<<grid_for((k + COMBINE_BLOCK - 1) / COMBINE_BLOCK, 64), 64, 0, s>>>(terms, k,
                                                                                   w.parts);
-    k_fast_total<<<1, 64, 0, s>>>(k, alpha, w.parts, d_est);
+    k_fast_total<<<1, 64, 0, s>>>(k, alpha, w.parts, d_probs ? w.flags : nullptr, d_est);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }

@@ -152,6 +152,56 @@ def test_spar_batch_matches_single_calls_and_oracle(env):
         assert (int(beta[i]), float(est[i]), int(kept[i])) == want == single, (kind, param, sd)
 
 
+def test_spar_batch_hip_graph_replays(env):
+    """Phase 2 of a replica batch captured once in a HIP graph and replayed
+    several times, with eager work between replays: every replay equals the
+    eager run and the single-replica calls."""
+    torch, api = env
+    nl, nr = 3_000, 15_000
+    l, r = gen.chung_lu(nl, nr, 150_000, 2.1, 2.3, 2000, seed=7)
+    g = api.Graph(nl, nr, l, r)
+    rb = api.ReplicaBatch(g, REPLICAS)
+    want_b, want_e = rb.run()
+    n = len(REPLICAS)
+    beta = torch.zeros(n, dtype=torch.int64, device="cuda")
+    est = torch.zeros(n, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        rb.run_async(beta, est, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rb.run_async(beta, est)
+    for i in range(4):
+        beta.fill_(-1)
+        est.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(beta.cpu().numpy().view(np.uint64), want_b), i
+        assert np.array_equal(est.cpu().numpy(), want_e), i
+        kind, param, sd = REPLICAS[i]
+        single = g.espar(param, sd) if kind == "espar" else g.clrspar(param, sd)
+        assert (int(want_b[i]), float(want_e[i]), int(rb.kept[i])) == single
+
+
+def test_spar_batch_rejects_foreign_sizes(env):
+    """Phase 2 laid out from another replica set's sizes marks every result
+    invalid instead of reading or writing outside its buffers."""
+    torch, api = env
+    nl, nr = 3_000, 15_000
+    l, r = gen.chung_lu(nl, nr, 150_000, 2.1, 2.3, 2000, seed=7)
+    g = api.Graph(nl, nr, l, r)
+    rb = api.ReplicaBatch(g, [("espar", 0.5, 1), ("clrspar", 4, 2)])
+    other = api.ReplicaBatch(g, [("espar", 0.5, 3), ("clrspar", 4, 4)])
+    # phase 2 of rb's seeds laid out (and its workspace sized) from other's sizes:
+    # the check on the device must fail
+    rb.info, rb.ws = other.info, other.ws
+    beta, est = rb.run()
+    assert np.all(beta == np.uint64(2**64 - 1)) and np.all(np.isnan(est))
+
+
 def test_spar_batch_edge_cases(env):
     torch, api = env
     from paper_1801_00338_amd._lib import BfcError
@@ -187,9 +237,11 @@ def test_full_replica_batch_256(env):
     for n in (4, 8, 16, 32):
         reps += [("clrspar", n, (4 << 32) | len(reps) + i) for i in range(32)]
     t0 = time.time()
-    beta, est, kept = g.spar_batch(reps, log=lambda msg: print(msg, flush=True))
+    rb = api.ReplicaBatch(g, reps, log=lambda msg: print(msg, flush=True))
+    beta, est = rb.run()
+    kept = rb.kept
     print(f"B={B}; batch of {len(reps)} replicas, {int(kept.sum())} kept edges, workspace "
-          f"{g.last_batch_ws_bytes / 1e9:.1f} GB, {time.time() - t0:.1f} s", flush=True)
+          f"{rb.ws_bytes / 1e9:.1f} GB, {time.time() - t0:.1f} s", flush=True)
     for grp in range(8):
         e = est[32 * grp:32 * grp + 32]
         kind, param, _ = reps[32 * grp]

@@ -105,3 +105,95 @@ def test_estimator_errors(api):
     cl, cr = oracle.per_vertex(4, 5, l, r)
     ids, cnt, est = g.vsamp(50, 2, np.concatenate([cl, cr]).astype(np.float64))
     assert est == 60.0
+
+
+def _combine(counts, weights, total, k, n, weighted):
+    """VSamp's estimate from per-draw counts, in the documented order: weighted,
+    term_i = count_i * (Q / (4 w_i)) summed left to right in blocks of 1,024
+    draws, the block sums left to right, over k; uniform, the exact integer
+    sum times n / (4 k)."""
+    if not weighted:
+        return (float(int(counts.sum(dtype=np.uint64))) * float(n)) / (4.0 * float(k))
+    t = counts.astype(np.float64) * (float(total) / (4.0 * weights.astype(np.float64)))
+    parts = [np.cumsum(t[b:b + 1024])[-1] for b in range(0, k, 1024)]
+    return float(np.cumsum(parts)[-1]) / float(k)
+
+
+def test_vsamp_draws_reproduce_vsamp(graph):
+    """The draws alone, with the oracle's per-vertex counts at the drawn ids,
+    give bfc_vsamp's ids, counts and estimate exactly (uniform and weighted)."""
+    nl, nr, l, r, g = graph
+    cl, cr = oracle.per_vertex(nl, nr, l, r)
+    cnt_all = np.concatenate([cl, cr])
+    rng = np.random.default_rng(5)
+    probs = rng.random(nl + nr) ** 2
+    probs[rng.random(nl + nr) < 0.1] = 0.0
+    for k in (1, 1023, 2500):
+        for pr in (None, probs):
+            seed = 1000 + k
+            ids, w, Q = g.vsamp_draws(k, seed, pr)
+            vi, vc, ve = g.vsamp(k, seed, pr)
+            assert np.array_equal(ids, vi)
+            counts = cnt_all[ids]
+            assert np.array_equal(counts, vc)
+            if pr is None:
+                assert Q == nl + nr and np.all(w == 1)
+            est = _combine(counts, w, Q, k, nl + nr, pr is not None)
+            assert est == ve, (k, pr is None, est, ve)
+
+
+def test_sparsifiers_and_vsamp_captured_in_one_hip_graph(graph):
+    """ESpar, ClrSpar and weighted VSamp queued without any host
+    synchronisation, captured once in a HIP graph and replayed with eager
+    work between the replays: every replay equals the oracle."""
+    import torch
+    nl, nr, l, r, g = graph
+    dev = g.device
+    rng = np.random.default_rng(21)
+    probs = torch.as_tensor(rng.random(nl + nr) ** 2).to(dev)
+    k = 1500
+    want_e = oracle.espar(nl, nr, l, r, 0.3, 77)
+    want_c = oracle.clrspar(nl, nr, l, r, 3, 78)
+    want_v = oracle.vsamp(nl, nr, l, r, k, 79, probs.cpu().numpy())
+    be, bc, bv = g.spar_buffers(), g.spar_buffers(), g.vsamp_buffers(k)
+
+    def queue():
+        g.espar_async(be, 0.3, 77)
+        g.clrspar_async(bc, 3, 78)
+        g.vsamp_async(bv, 79, probs)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        queue()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    hg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(hg):
+        queue()
+    for i in range(3):
+        for t in (be["out"], bc["out"], bv["cnt"], bv["ids"]):
+            t.fill_(-1)
+        hg.replay()
+        torch.cuda.synchronize()
+        assert g.spar_result(be) == want_e, i
+        assert g.spar_result(bc) == want_c, i
+        ids = bv["ids"].cpu().numpy().view(np.uint32)[:k]
+        cnt = bv["cnt"].cpu().numpy().view(np.uint64)[:k]
+        assert np.array_equal(ids, want_v[0]) and np.array_equal(cnt, want_v[1]), i
+        assert float(bv["est"].item()) == want_v[2], i
+        assert g.espar(0.5, 5) == oracle.espar(nl, nr, l, r, 0.5, 5)   # eager work between
+
+
+def test_invalid_probabilities_give_nan_without_synchronising(api):
+    import torch
+    l, r = gen.biclique(4, 5)
+    g = api.Graph(4, 5, l, r)
+    buf = g.vsamp_buffers(10)
+    bad = torch.tensor(np.r_[np.ones(8), -1.0], dtype=torch.float64, device=g.device)
+    g.vsamp_async(buf, 1, bad)
+    torch.cuda.synchronize()
+    assert np.isnan(float(buf["est"].item()))
+    from paper_1801_00338_amd._lib import BfcError
+    with pytest.raises(BfcError, match="PROBS"):
+        g.check_probs(bad)

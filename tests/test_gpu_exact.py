@@ -167,3 +167,94 @@ def test_local_wide_table_modes(api):
     assert np.array_equal(cl, ol) and np.array_equal(cr, orr)
     assert np.array_equal(ce, oracle.per_edge(nl, nr, l, r))
     assert g.exact() == oracle.exact(nl, nr, l, r)[0]
+
+
+# ------------------------------------------------------------------ hash-table starts
+OFF = 0xFFFFFFFF
+HASH_TUNINGS = [
+    dict(hash_small_max=OFF, hash_mid_max=OFF),          # dense windows only
+    dict(),                                              # defaults
+    dict(hash_mid_max=OFF, hash_max_density=1 << 30),          # small tables only
+    dict(hash_small_max=OFF, hash_max_density=1 << 30),        # mid tables only
+    dict(hash_passes=1, hash_max_density=1 << 30),             # one pass: full tables fall back
+    dict(hash_passes=4, hash_max_density=1 << 30),             # every start in four partitions
+    dict(hash_small_max=64, hash_mid_max=300, hash_max_density=1 << 30),
+]
+
+
+def _hash_graphs():
+    rng = np.random.default_rng(42)
+    out = []
+    l, r = rand_graph(rng, 40, 50, 900)
+    out.append(("random 40x50", 40, 50, l, r))
+    nl, nr = 200_000, 150_000          # sparse ends spread over many windows
+    l, r = gen.chung_lu(nl, nr, 600_000, 2.2, 2.4, 5000, seed=11)
+    out.append(("chung_lu 200k/150k/600k", nl, nr, l, r))
+    nl, nr = 20_000, 60_000            # power law with hubs: all four classes
+    l, r = gen.chung_lu(nl, nr, 600_000, 2.1, 2.3, 5_000, seed=71)
+    out.append(("chung_lu 20k/60k/600k", nl, nr, l, r))
+    l, r = gen.biclique(40, 60)        # 60 midpoints, every start T = 60 * (rank above)
+    out.append(("K_40,60", 40, 60, l, r))
+    return out
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_hash_classes_against_oracle(api, case):
+    """The hash-table walk, the dense windows and the fallback of full tables
+    all give the oracle's count, from both sides, under every class split."""
+    name, nl, nr, l, r = _hash_graphs()[case]
+    g = api.Graph(nl, nr, l, r)
+    want = oracle.exact(nl, nr, l, r)[0]
+    for t in HASH_TUNINGS:
+        print(f"{name}: {t}", flush=True)
+        assert g.exact_tuned(t) == want, t
+        for side in (1, 2):
+            assert g.exact_tuned(t, side=side) == want, (t, side)
+
+
+def test_hash_full_table_falls_back(api):
+    """A start whose single pass overflows the 1,024-slot table (2,001
+    distinct end points, each reached once) is counted by the narrow walk
+    instead; with automatic passes it fits in four partitions."""
+    # L: u = 0, a_i = 1..1000, b_i = 1001..2000, u' = 2001 (all of degree 2);
+    # R: x = 0, y = 1, z_i = 1 + i (shared by a_i and b_i)
+    a = np.arange(1, 1001, dtype=np.uint32)
+    b = np.arange(1001, 2001, dtype=np.uint32)
+    z = np.arange(2, 1002, dtype=np.uint32)
+    l = np.concatenate([[0, 0, 2001, 2001], a, a, b, b]).astype(np.uint32)
+    r = np.concatenate([[0, 1, 0, 1], np.zeros(1000), z, np.ones(1000), z]).astype(np.uint32)
+    nl, nr = 2002, 1002
+    g = api.Graph(nl, nr, l, r)
+    want = oracle.exact(nl, nr, l, r)[0]
+    dense = 1 << 30                    # every start counts as sparse
+    for t in (dict(hash_passes=1, hash_max_density=dense),
+              dict(hash_passes=2, hash_max_density=dense), dict(hash_max_density=dense), {}):
+        print(f"fallback case: {t}", flush=True)
+        assert g.exact_tuned(t, side=1) == want, t
+        assert g.exact_tuned(t, side=2) == want, t
+
+
+# ------------------------------------------------------------------ hub starts split over workgroups
+@pytest.mark.parametrize("case", ["windows", "hubs"])
+def test_local_counts_with_split_hub_starts(api, case):
+    """Local counts with hub starts cut into runs of counter windows walked by
+    different workgroups (down to one window per part) equal the oracle's
+    per-vertex and per-edge counts."""
+    if case == "windows":
+        nl, nr = 200_000, 150_000
+        l, r = gen.chung_lu(nl, nr, 600_000, 2.2, 2.4, 5000, seed=11)
+    else:
+        nl, nr = 100_000, 60_000
+        l, r = gen.chung_lu(nl, nr, 1_000_000, 2.1, 2.1, 20_000, seed=23)
+    g = api.Graph(nl, nr, l, r)
+    ol, orr = oracle.per_vertex(nl, nr, l, r)
+    oe = oracle.per_edge(nl, nr, l, r)
+    for split in (0, 1, 1000, 100_000):
+        print(f"{case}: split {split}", flush=True)
+        cl, cr, ce = g.local_split(split)
+        assert np.array_equal(cl, ol), split
+        assert np.array_equal(cr, orr), split
+        assert np.array_equal(ce, oe), split
+    # vertex counts only (no second look at the final counts)
+    cl, cr, _ = g.local_split(1, edges=False)
+    assert np.array_equal(cl, ol) and np.array_equal(cr, orr)
