@@ -132,6 +132,19 @@ int bfc_exact_plan(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes,
 int bfc_exact_count(const bfc_graph *g, int side, uint64_t *d_total,
                     void *d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): bfc_exact
+ * with the same kernels and result, its workspace taken from a static device
+ * array of BFC_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends.  The call allocates nothing.  It runs on
+ * the current device, asynchronously on `stream`.  BFC_E_TOO_LARGE when the
+ * graph needs a larger workspace (bfc_exact_ws_size; 128 MiB holds graphs of
+ * about 3.5 million edges).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other host threads) race, and
+ * the caller must order them. */
+#define BFC_NOALLOC_SCRATCH_BYTES (128u << 20)
+int bfc_exact_noalloc(const bfc_graph *g, int side, uint64_t *d_total, hipStream_t stream);
+
 /* ---------------------------------------------------------------------- */
 /* Local counts (Sec. 2 definitions; Eq. (2); vBFC and eBFC of Sec. 4.2).   */
 /*   B_v = sum over same-side w != v of C(|N(v) & N(w)|, 2)                 */

@@ -92,6 +92,7 @@ SIGNATURES = {
                        C.c_int),
     "bfc_exact_count": ([C.POINTER(bfc_graph), C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
                          C.c_void_p], C.c_int),
+    "bfc_exact_noalloc": ([C.POINTER(bfc_graph), C.c_int, C.c_void_p, C.c_void_p], C.c_int),
     "bfc_local_ws_size": ([C.POINTER(bfc_graph), C.POINTER(C.c_size_t)], C.c_int),
     "bfc_local": ([C.POINTER(bfc_graph), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                    C.c_size_t, C.c_void_p], C.c_int),

@@ -31,6 +31,8 @@
 //
 // Scheduling.  Starts are bucketed by their wedge count (log2) and handed out
 // largest first through an atomic queue per class to persistent grids.
+#include <mutex>
+
 #include "common.h"
 
 namespace bfc {
@@ -1968,6 +1970,48 @@ out:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+// ------------------------------------------------------------------ no-allocation variant
+// bfc_exact with its workspace in a static device array: one copy per GPU,
+// held until the process ends.  Host code never uses the array's name as an
+// address (in host code it is only a stand-in for the symbol); the device
+// address of each GPU's copy is looked up once with hipGetSymbolAddress while
+// that GPU is current and kept per device.
+static __device__ __align__(256) unsigned char scratch[BFC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES];
+}  // namespace
+
+static int scratch_ptr(void **out) {
+    int dev = 0;
+    BFC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return BFC_E_ARG;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *ptr = nullptr;
+        BFC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || !aligned256(ptr)) return BFC_E_ALIGN;
+        scratch_dev[dev] = ptr;
+    }
+    *out = scratch_dev[dev];
+    return BFC_OK;
+}
+
+int bfc_exact_noalloc(const bfc_graph *g, int side, uint64_t *d_total, hipStream_t s) {
+    if (!g || !d_total) return BFC_E_NULL;
+    size_t need = 0;
+    BFC_TRY(bfc_exact_ws_size(g, side, &need));
+    if (need > (size_t)BFC_NOALLOC_SCRATCH_BYTES) return BFC_E_TOO_LARGE;
+    void *ws = nullptr;
+    BFC_TRY(scratch_ptr(&ws));
+    // every workspace value the count uses is written by this call's plan
+    // kernels first (the queue state is cleared by a kernel, not a memset),
+    // so what an earlier call left in the array does not matter
+    return bfc_exact(g, side, d_total, ws, (size_t)BFC_NOALLOC_SCRATCH_BYTES, s);
 }
 
 int bfc_local_ws_size(const bfc_graph *g, size_t *bytes) {
