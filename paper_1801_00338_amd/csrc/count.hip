@@ -322,7 +322,7 @@ struct LocalArgs {
     const uint32_t *eidA, *idA;
     unsigned long long *cntA;     // per start-side vertex (caller ids), or null
     unsigned long long *cntE;     // per edge (caller order), or null
-    unsigned long long *twiceB;   // 2 B_v per midpoint rank (workspace)
+    unsigned long long *epos;     // B_(u,v) by A-side adjacency position (workspace), or null
     int pass2;                    // edge / midpoint sums wanted (else B_u only)
     // wide starts split over several workgroups: item it covers part
     // wide_g[it] & 0xFFFF of wide_g[it] >> 16 (equal runs of table windows);
@@ -351,9 +351,10 @@ struct WideScratch {
 // Per-edge and per-midpoint output of one (start, midpoint) pair.
 __device__ inline void emit_edge(const LocalArgs &a, uint32_t k, uint32_t v, uint32_t dv,
                                  unsigned long long s) {
-    unsigned long long e = s - (unsigned long long)(dv - 1);
+    (void)v;
+    const unsigned long long e = s - (unsigned long long)(dv - 1);
     if (a.cntE) a.cntE[a.eidA[k]] = e;
-    if (e) atomicAdd(&a.twiceB[v], e);
+    if (a.epos) a.epos[k] = e;
 }
 
 // A group: 4 consecutive adjacency entries at `base` (16-byte aligned), of
@@ -1464,12 +1465,20 @@ __global__ __launch_bounds__(256) void k_part_sums(const unsigned long long *per
     }
 }
 
-// B_v of the midpoint side from the edge sums; outputs in caller ids.
-__global__ void k_local_finish(const unsigned long long *twiceB, const uint32_t *idB, uint32_t nB,
-                               unsigned long long *cntB) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < nB;
-         v += (uint64_t)gridDim.x * blockDim.x)
-        cntB[idB[v]] = twiceB[v] >> 1;
+// B_v of the midpoint side: half the sum of its edges' counts (each
+// butterfly through v uses two edges of v), read through the B-side row's
+// cross positions; one wave per row, outputs in caller ids.
+__global__ __launch_bounds__(256) void k_local_finish(const uint32_t *offB, const uint32_t *xB,
+                                                      const unsigned long long *epos,
+                                                      const uint32_t *idB, uint32_t nB,
+                                                      unsigned long long *cntB) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
+    for (uint32_t v = blockIdx.x * wpb + threadIdx.x / WAVE; v < nB; v += gridDim.x * wpb) {
+        unsigned long long t = 0;
+        for (uint32_t p = offB[v] + lane; p < offB[v + 1]; p += WAVE) t += epos[xB[p]];
+        t = wave_sum64(t);
+        if (lane == 0) cntB[idB[v]] = t >> 1;
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -1636,14 +1645,14 @@ static int exact_setup(const bfc_graph *g, int side, void *d_ws, size_t ws_bytes
 // sums of split starts, and each wide workgroup's slice of cursor state.
 struct LocalWs {
     ExactWs e;
-    unsigned long long *twiceB, *esum_g;
+    unsigned long long *epos, *esum_g;
     WideScratch slices;
 };
 
 static LocalWs carve_local(Carver &c, const Plan &p, unsigned wide_groups) {
     LocalWs w;
     w.e = carve_exact(c, p);
-    w.twiceB = c.take<unsigned long long>(pad64(p.nB));
+    w.epos = c.take<unsigned long long>(pad64(p.m));
     w.esum_g = c.take<unsigned long long>(pad64(p.m));
     const uint64_t stride = pad64(p.max_deg_A);
     const uint64_t n = (uint64_t)wide_groups * stride;
@@ -1712,7 +1721,7 @@ int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt
                        *ce = (unsigned long long *)d_cnt_e;
     unsigned long long *cntB = p.start_r ? cl : cr;
     const bool pass2 = ce != nullptr || cntB != nullptr;
-    k_zero_u64<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.nB);
+    if (cntB) k_zero_u64<<<grid_for(p.m), 256, 0, s>>>(w.epos, p.m);
     k_zero_u32<<<grid_for(p.nA), 256, 0, s>>>(w.e.wdone, p.nA);
     if (pass2) k_zero_u64<<<grid_for(p.m), 256, 0, s>>>(w.esum_g, p.m);
     BFC_HIP(hipGetLastError());
@@ -1724,7 +1733,7 @@ int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt
     a.idA = p.start_r ? g->id_r : g->id_l;
     a.cntA = p.start_r ? cr : cl;
     a.cntE = ce;
-    a.twiceB = w.twiceB;
+    a.epos = cntB ? w.epos : nullptr;
     a.pass2 = pass2;
     a.wide_g = w.e.wide_g;
     a.wdone = w.e.wdone;
@@ -1732,8 +1741,9 @@ int local_run(const bfc_graph *g, int side, const uint8_t *mark, uint64_t *d_cnt
     k_local_narrow<<<gn, WT, 0, s>>>(a);
     k_local_wide<<<gw, NT, 0, s>>>(a, w.slices);
     if (cntB)
-        k_local_finish<<<grid_for(p.nB), 256, 0, s>>>(w.twiceB, p.start_r ? g->id_l : g->id_r,
-                                                       p.nB, cntB);
+        k_local_finish<<<grid_for(p.nB, 4) < 8192 ? grid_for(p.nB, 4) : 8192, 256, 0, s>>>(
+            p.offB, p.start_r ? g->xpos_l : g->xpos_r, w.epos, p.start_r ? g->id_l : g->id_r,
+            p.nB, cntB);
     BFC_HIP(hipGetLastError());
     return BFC_OK;
 }
