@@ -136,8 +136,9 @@ struct QueueState {
 // Bucket = bit length of that count (0 = nothing to do); class 1 = wide.
 // Class: wide when d_u > narrow_max, else hash when the wedges fit the
 // small (<= hs_max) or mid (<= hm_max) tables, else narrow.  With split != 0
-// a wide start is cut into ceil(wedges / split) parts (at most one per table
-// window and SPLIT_MAX), each an item of its own (nsplit[u] parts).
+// (local counts) a start of more than `split` wedges is wide too, and a wide
+// start is cut into ceil(wedges / split) parts (at most one per table window
+// and SPLIT_MAX), each an item of its own (nsplit[u] parts).
 // A narrow start takes a hash table only when it is sparse: at most
 // hl.density wedges (default HASH_DENSITY) per counter window its end points
 // span (the window walk pays about one round trip per window it touches).
@@ -179,7 +180,9 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
             uint32_t b = t ? 64 - __clzll(t) : 0;
             const uint32_t span = (top >> G_SHIFT) - (u >> G_SHIFT) + 1;
             const bool spread = t <= (uint64_t)density * span;
-            uint32_t cls = (re - rb) > narrow_max ? CLS_WIDE
+            // with split, a start of more than one part's wedges takes the wide
+            // kernel (whatever its degree), so that its parts can run side by side
+            uint32_t cls = ((re - rb) > narrow_max || (split && t > split)) ? CLS_WIDE
                          : !spread ? CLS_NARROW
                          : t <= hs_max ? CLS_HASH1 : t <= hm_max ? CLS_HASH2 : CLS_NARROW;
             uint32_t G = 1;
@@ -1491,10 +1494,15 @@ struct ExactWs {
 };
 
 // Items of the wide class: one per start, plus the extra parts of split
-// starts (at most 2 * wedges / SPLIT_WEDGES in all: every start's all-ends
-// wedges add up to twice the wedges).
+// starts: at most 2 * wedges / split in all (every start's all-ends wedges
+// add up to twice the wedges), and at most one per further table window.
 static inline size_t wide_items_cap(const Plan &p) {
-    return pad64(p.nA) + (p.split ? (size_t)(2 * (p.wedges / p.split)) : 0) + 64;
+    if (!p.split) return pad64(p.nA) + 64;
+    // extra parts: at most all-ends wedges / split, and at most one per
+    // further table window of every start
+    const uint64_t by_wedges = 2 * (p.wedges / p.split);
+    const uint64_t by_windows = (uint64_t)p.nA * (p.nA ? ((p.nA - 1) >> G_SHIFT) : 0);
+    return pad64(p.nA) + (size_t)(by_wedges < by_windows ? by_wedges : by_windows) + 64;
 }
 
 static ExactWs carve_exact(Carver &c, const Plan &p) {
