@@ -872,12 +872,13 @@ def main():
         "exact_wedges_per_s": W / (exact_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_exact_narrow + k_exact_wide (one exact count)",
+                     "kernel": ("k_exact_hash_small + k_exact_hash_mid + k_exact_narrow + "
+                                "k_exact_wide (one exact count)"),
                      "alg_bytes_per_launch": alg_bytes},
         "roofline_local": {"bound": "hbm", "achieved": achieved_local, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved_local / HBM_PEAK_GBS,
                            "traffic": traffic_from_profiles(w.name, "k_local"),
-                           "kernel": "k_local_narrow + k_local_wide (+ plan and finish)",
+                           "kernel": "k_local_narrow + k_local_wide + k_local_finish (+ plan)",
                            "alg_bytes_per_launch": alg_local,
                            "design_bytes_per_launch": design_local},
     }
