@@ -142,16 +142,19 @@ struct QueueState {
 // A narrow start takes a hash table only when it is sparse: at most
 // hl.density wedges (default HASH_DENSITY) per counter window its end points
 // span (the window walk pays about one round trip per window it touches).
+// A start of at most half_density wedges per spanned window is marked
+// (bucket bit 15) for the narrow walk's short pieces.
 constexpr uint64_t SPLIT_WEDGES = 1ull << 24;  // local counts: wedges per part of a wide start
 constexpr uint32_t SPLIT_MAX = 4096;
-constexpr uint32_t HASH_DENSITY = 64;
+constexpr uint32_t HASH_DENSITY = 64, HALF_DENSITY = 384;
+constexpr uint16_t BUCKET_SPARSE = 0x8000;
 __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32_t *adjA,
                                               const uint32_t *xA, const uint32_t *offB,
                                               const uint32_t *adjB,
                                               uint32_t nA, int all_ends, const uint8_t *mark,
                                               uint32_t narrow_max, uint32_t hs_max,
                                               uint32_t hm_max, uint32_t density,
-                                              uint64_t split,
+                                              uint32_t half_density, uint64_t split,
                                               uint16_t *bucket, uint16_t *nsplit,
                                               QueueState *q) {
     __shared__ uint32_t hist[NCLASS][NBUCKET];
@@ -163,23 +166,29 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
         uint32_t rb = offA[u], re = offA[u + 1];
         if (mark && !mark[u]) re = rb;          // start not asked for
         unsigned long long t = 0;
-        uint32_t top = 0;                       // highest end point rank
+        uint32_t top = 0, bot = INF;            // highest and lowest end point rank
+        const bool spans = (hs_max | hm_max | half_density) != 0u;
         for (uint32_t k = rb + lane; k < re; k += WAVE) {
             uint32_t v = adjA[k];
             const uint32_t e = offB[v + 1];
             t += e - (all_ends ? offB[v] : xA[k]) - 1;
-            if (hs_max | hm_max) top = max(top, adjB[e - 1]);
+            if (spans) {
+                top = max(top, adjB[e - 1]);
+                if (all_ends) bot = min(bot, adjB[offB[v]]);
+            }
         }
         t = wave_sum64(t);
         top = wave_incl_max(top);
         top = wave_last(top);
+        bot = all_ends ? wave_min(bot) : u;
         // a start with one midpoint shares at most one with any w: C_u[w] <= 1
         // adds nothing to a count, so it is not queued (its outputs stay 0)
         if (re - rb < 2) t = 0;
         if (lane == 0) {
             uint32_t b = t ? 64 - __clzll(t) : 0;
-            const uint32_t span = (top >> G_SHIFT) - (u >> G_SHIFT) + 1;
+            const uint32_t span = top >= bot ? (top >> G_SHIFT) - (bot >> G_SHIFT) + 1 : 1u;
             const bool spread = t <= (uint64_t)density * span;
+            const bool sparse = t <= (uint64_t)half_density * span;
             // with split, a start of more than one part's wedges takes the wide
             // kernel (whatever its degree), so that its parts can run side by side
             uint32_t cls = ((re - rb) > narrow_max || (split && t > split)) ? CLS_WIDE
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
                 gg = gg < SPLIT_MAX ? gg : SPLIT_MAX;
                 G = gg > 1 ? (uint32_t)gg : 1u;
             }
-            bucket[u] = (uint16_t)(b | cls << 8);
+            bucket[u] = (uint16_t)(b | cls << 8) | (sparse ? BUCKET_SPARSE : 0);
             if (nsplit) nsplit[u] = (uint16_t)G;
             if (b) atomicAdd(&hist[cls][b], G);
         }
@@ -242,7 +251,7 @@ __global__ __launch_bounds__(256) void k_scatter_items(const uint16_t *bucket, u
         uint32_t b = 0, cls = 0, local = 0, G = 1;
         if (u < nA) {
             b = bucket[u] & 255u;
-            cls = bucket[u] >> 8;
+            cls = (bucket[u] >> 8) & (NCLASS - 1);
             if (cls == CLS_WIDE && items.nsplit) G = items.nsplit[u];
             if (b) local = atomicAdd(&hist[cls][b], G);
         }
@@ -305,6 +314,7 @@ struct CountArgs {
     const uint32_t *seg1, *seg_start, *seg_win;
     const uint32_t *items, *items_wide, *items_h1, *items_h2;
     uint32_t *ovf;                      // hash starts handed back to the narrow walk
+    const uint16_t *bucket;             // per start: work bucket, class, BUCKET_SPARSE
     QueueState *q;
     uint32_t nA;
     uint32_t chunk;                     // narrow starts per queue access
@@ -375,8 +385,13 @@ __device__ inline uint32_t group_mask(uint32_t base, uint32_t lo, uint32_t hi, u
 // ------------------------------------------------------------------ narrow: one wave per start
 // A window's sub-runs are cut into pieces of WK consecutive groups (16
 // entries) of one midpoint; lanes take pieces round-robin, so one search maps
-// a piece to its midpoint and the entries of a piece are contiguous.
-constexpr int WK = 4;
+// a piece to its midpoint and the entries of a piece are contiguous.  The
+// narrow walk of a start whose windows are sparse (few wedges per window its
+// end points span, marked by the plan) cuts pieces of WK_SPARSE groups: a
+// window's work is then spread over more lanes and each lane's counter
+// updates (whose cost does not depend on how many of its entries are in the
+// sub-run) are halved.
+constexpr int WK = 4, WK_SPARSE = 2;
 
 template <bool LOCAL>
 struct WShared {
@@ -394,7 +409,7 @@ struct Piece {
     uint32_t base, lo, len, skip, j;
 };
 
-template <bool LOCAL>
+template <bool LOCAL, int K = WK>
 __device__ inline Piece wpiece(const WShared<LOCAL> &sh, uint32_t du, uint32_t pi, bool valid) {
     // branch-free search over the du midpoint prefixes (uniform trip count)
     uint32_t j = 0;
@@ -406,8 +421,8 @@ __device__ inline Piece wpiece(const WShared<LOCAL> &sh, uint32_t du, uint32_t p
     j -= 1;
     Piece pc;
     const uint32_t lo = sh.lo[j], hi = sh.hi[j];
-    const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * WK;
-    const uint32_t end = min(hi, (g0 + WK) << 2);
+    const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * K;
+    const uint32_t end = min(hi, (g0 + K) << 2);
     pc.base = valid ? g0 << 2 : 0;
     pc.lo = lo;
     pc.len = valid ? end - lo : 0;
@@ -420,14 +435,14 @@ __device__ inline Piece wpiece(const WShared<LOCAL> &sh, uint32_t du, uint32_t p
 // table holds 1 + midpoint at each midpoint's first piece; a wave max-scan
 // carries it over that midpoint's other pieces (midpoints and their first
 // pieces increase together).
-template <bool LOCAL>
+template <bool LOCAL, int K = WK>
 __device__ inline Piece wpiece_direct(const WShared<LOCAL> &sh, uint32_t lane, bool valid) {
     const uint32_t o = wave_incl_max(sh.own[lane]);
     const uint32_t j = min((o ? o : 1u) - 1, (uint32_t)(WSLOTS * WT - 1));
     Piece pc;
     const uint32_t lo = sh.lo[j], hi = sh.hi[j];
-    const uint32_t g0 = (lo >> 2) + (lane - sh.pre[j]) * WK;
-    const uint32_t end = min(hi, (g0 + WK) << 2);
+    const uint32_t g0 = (lo >> 2) + (lane - sh.pre[j]) * K;
+    const uint32_t end = min(hi, (g0 + K) << 2);
     pc.base = valid ? g0 << 2 : 0;
     pc.lo = lo;
     pc.len = valid ? end - lo : 0;
@@ -456,14 +471,14 @@ __device__ inline uint32_t wslot(const Piece &pc, uint32_t i, uint32_t w, uint32
 // NIB: 4-bit counters (starts of degree <= 15, so C_u[w] <= 15 and an
 // increment never carries into the next counter), eight per word; entry
 // slots are then nibble indices and the zero word is nibbles 8 z .. 8 z + 7.
-template <bool LOCAL, bool NIB = false>
+template <bool LOCAL, bool NIB = false, int K = WK>
 __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
     constexpr uint32_t PER = NIB ? 8 : 4, LOGP = NIB ? 3 : 2, BITS = NIB ? 4 : 8;
     constexpr uint32_t MASK = (1u << BITS) - 1;
     const uint32_t zb = (WTBL_WORDS + threadIdx.x) * PER;
-    uint32_t old[4 * WK], sft[4 * WK];
+    uint32_t old[4 * K], sft[4 * K];
 #pragma unroll
-    for (int k = 0; k < WK; k++) {
+    for (int k = 0; k < K; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -477,22 +492,22 @@ __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint
     // flight before the first result is waited for: an empty volatile asm
     // that takes each result (no instruction is emitted).
 #pragma unroll
-    for (int k = 0; k < 4 * WK; k++) asm volatile("" : "+v"(old[k]));
+    for (int k = 0; k < 4 * K; k++) asm volatile("" : "+v"(old[k]));
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < 4 * WK; k++) s += (old[k] >> sft[k]) & MASK;
+    for (int k = 0; k < 4 * K; k++) s += (old[k] >> sft[k]) & MASK;
     return s;
 }
 
 // Sum of the counters of the piece's entries.
-template <bool LOCAL, bool NIB = false>
+template <bool LOCAL, bool NIB = false, int K = WK>
 __device__ inline uint32_t wread(const WShared<LOCAL> &sh, const Piece &pc, const uint4 *q,
                                  uint32_t wb) {
     const uint8_t *t8 = (const uint8_t *)sh.tbl;
     const uint32_t zb = (WTBL_WORDS + threadIdx.x) * (NIB ? 8 : 4);
-    uint32_t v[4 * WK];
+    uint32_t v[4 * K];
 #pragma unroll
-    for (int k = 0; k < WK; k++) {
+    for (int k = 0; k < K; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -502,18 +517,18 @@ __device__ inline uint32_t wread(const WShared<LOCAL> &sh, const Piece &pc, cons
     }
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < 4 * WK; k++) s += v[k];
+    for (int k = 0; k < 4 * K; k++) s += v[k];
     return s;
 }
 
 // Clear the piece's counters (nibbles: an atomic and, since other lanes may
 // clear the word's other nibbles at the same time).
-template <bool LOCAL, bool NIB = false>
+template <bool LOCAL, bool NIB = false, int K = WK>
 __device__ inline void wclear(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
     uint8_t *t8 = (uint8_t *)sh.tbl;
     const uint32_t zb = (WTBL_WORDS + threadIdx.x) * (NIB ? 8 : 4);
 #pragma unroll
-    for (int k = 0; k < WK; k++) {
+    for (int k = 0; k < K; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -548,7 +563,7 @@ __device__ inline void wave_sync() {
 // sub-run of a table window is then one segment or two consecutive ones, so
 // the slot looks two segments ahead (w2/s2, w3/s3).  Windows are indexed in
 // table units (segment window >> LOGW).
-template <bool LOCAL, bool NIB>
+template <bool LOCAL, bool NIB, int K>
 __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, uint32_t rb,
                                         uint32_t du, bool pass2) {
     constexpr int LOGW = NIB ? 1 : 0;
@@ -614,7 +629,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             const bool two = NIB && act && h1 < ev[s] && w2[s] == kw;
             const uint32_t h = two ? (s2[s] < ev[s] ? s2[s] : ev[s]) : h1;
             const uint32_t lo = act ? p[s] : 0u, hi = act ? h : 0u;
-            const uint32_t np = act ? (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK : 0u;
+            const uint32_t np = act ? (((hi + 3) >> 2) - (lo >> 2) + K - 1) / K : 0u;
             const bool adv = act && h < ev[s];
             p[s] = act ? h : p[s];
             cur[s] += adv ? (two ? 2u : 1u) : 0u;
@@ -657,14 +672,14 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
 
     // Bump, second look and clear of one window held in registers.
     auto finish = [&](const Piece &pc, const uint4 *q, uint32_t wb) -> uint32_t {
-        const uint32_t part = wbump<LOCAL, NIB>(sh, pc, q, wb);
+        const uint32_t part = wbump<LOCAL, NIB, K>(sh, pc, q, wb);
         if (LOCAL && pass2) {
             wave_order();
-            const uint32_t v = wread<LOCAL, NIB>(sh, pc, q, wb);
+            const uint32_t v = wread<LOCAL, NIB, K>(sh, pc, q, wb);
             if (v) atomicAdd(&sh.esum[pc.j], (unsigned long long)v);
         }
         wave_order();
-        wclear<LOCAL, NIB>(sh, pc, q, wb);
+        wclear<LOCAL, NIB, K>(sh, pc, q, wb);
         wave_order();
         return part;
     };
@@ -680,7 +695,7 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
     uint32_t NP = next_window(kw);
     wave_order();
     Piece pa, pb;
-    uint4 qa[WK], qb[WK];
+    uint4 qa[K], qb[K];
     while (kw != INF) {
         if (NP > (uint32_t)WT) {
             // Rounds of 64 pieces.  Round r's pieces are mapped to midpoints
@@ -706,8 +721,8 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
                 const bool valid = pi < NP;
                 Piece pc;
                 const uint32_t lo = sh.lo[j], hi = sh.hi[j];
-                const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * WK;
-                const uint32_t end = min(hi, (g0 + WK) << 2);
+                const uint32_t g0 = (lo >> 2) + (pi - sh.pre[j]) * K;
+                const uint32_t end = min(hi, (g0 + K) << 2);
                 pc.base = valid ? g0 << 2 : 0;
                 pc.lo = lo;
                 pc.len = valid ? end - lo : 0;
@@ -719,24 +734,24 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             for (int pass = 0; pass < ((LOCAL && pass2) ? 2 : 1); pass++) {
                 uint32_t carry = 0, part = 0;
                 Piece r0p = map_round(0, carry);
-                uint4 q0[WK], q1[WK];
-                wfetch<WK>(a.adjB, r0p, q0);
+                uint4 q0[K], q1[K];
+                wfetch<K>(a.adjB, r0p, q0);
                 for (uint32_t r = 0;; r += 2) {
                     Piece r1p = map_round(r + 1, carry);
-                    wfetch<WK>(a.adjB, r1p, q1);
+                    wfetch<K>(a.adjB, r1p, q1);
                     if (pass == 0) {
-                        part += wbump<LOCAL, NIB>(sh, r0p, q0, wb);
+                        part += wbump<LOCAL, NIB, K>(sh, r0p, q0, wb);
                     } else {
-                        const uint32_t v = wread<LOCAL, NIB>(sh, r0p, q0, wb);
+                        const uint32_t v = wread<LOCAL, NIB, K>(sh, r0p, q0, wb);
                         if (v) atomicAdd(&sh.esum[r0p.j], (unsigned long long)v);
                     }
                     if (r + 1 >= rounds) break;
                     r0p = map_round(r + 2, carry);
-                    wfetch<WK>(a.adjB, r0p, q0);
+                    wfetch<K>(a.adjB, r0p, q0);
                     if (pass == 0) {
-                        part += wbump<LOCAL, NIB>(sh, r1p, q1, wb);
+                        part += wbump<LOCAL, NIB, K>(sh, r1p, q1, wb);
                     } else {
-                        const uint32_t v = wread<LOCAL, NIB>(sh, r1p, q1, wb);
+                        const uint32_t v = wread<LOCAL, NIB, K>(sh, r1p, q1, wb);
                         if (v) atomicAdd(&sh.esum[r1p.j], (unsigned long long)v);
                     }
                     if (r + 2 >= rounds) break;
@@ -751,8 +766,8 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             continue;
         }
         // prologue: window kw into (pa, qa), publish the following one
-        pa = wpiece_direct(sh, lane, lane < NP);
-        wfetch<WK>(a.adjB, pa, qa);
+        pa = wpiece_direct<LOCAL, K>(sh, lane, lane < NP);
+        wfetch<K>(a.adjB, pa, qa);
         uint32_t kwa = kw;
         wave_order();
         NP = next_window(kw);
@@ -763,8 +778,8 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             // without a piece reads the first group) so that no branch
             // joins the buffers while their loads are in flight
             bool more = kw != INF && NP <= (uint32_t)WT;
-            pb = wpiece_direct(sh, lane, more && lane < NP);
-            wfetch<WK>(a.adjB, pb, qb);
+            pb = wpiece_direct<LOCAL, K>(sh, lane, more && lane < NP);
+            wfetch<K>(a.adjB, pb, qb);
             sum += finish(pa, qa, kwa << (G_SHIFT + LOGW));
             if (!more) break;
             const uint32_t kwb = kw;
@@ -772,8 +787,8 @@ __device__ unsigned long long wave_walk(const CountArgs &a, WShared<LOCAL> &sh, 
             wave_order();
             // (pb, qb) hold window kwb; window kw is published
             more = kw != INF && NP <= (uint32_t)WT;
-            pa = wpiece_direct(sh, lane, more && lane < NP);
-            wfetch<WK>(a.adjB, pa, qa);
+            pa = wpiece_direct<LOCAL, K>(sh, lane, more && lane < NP);
+            wfetch<K>(a.adjB, pa, qa);
             sum += finish(pb, qb, kwb << (G_SHIFT + LOGW));
             if (!more) break;
             kwa = kw;
@@ -831,8 +846,12 @@ __global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
         b++;
         const uint32_t rb = a.offA[u];
         const uint32_t du = a.offA[u + 1] - rb;
-        const unsigned long long s = du <= 15u ? wave_walk<false, true>(a, sh, rb, du, false)
-                                               : wave_walk<false, false>(a, sh, rb, du, false);
+        const bool sp = (a.bucket[u] & BUCKET_SPARSE) != 0;
+        const unsigned long long s =
+            du <= 15u ? (sp ? wave_walk<false, true, WK_SPARSE>(a, sh, rb, du, false)
+                            : wave_walk<false, true, WK>(a, sh, rb, du, false))
+                      : (sp ? wave_walk<false, false, WK_SPARSE>(a, sh, rb, du, false)
+                            : wave_walk<false, false, WK>(a, sh, rb, du, false));
         if (a.per_start) {
             const unsigned long long t = wave_sum64(s);
             if (threadIdx.x == 0) a.per_start[u] = t;
@@ -854,8 +873,12 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
         for (uint32_t it = b; it < e; it++) {
             const uint32_t u = a.c.items[it];
             const uint32_t rb = a.c.offA[u], du = a.c.offA[u + 1] - rb;
-            unsigned long long s = du <= 15u ? wave_walk<true, true>(a.c, sh, rb, du, a.pass2)
-                                             : wave_walk<true, false>(a.c, sh, rb, du, a.pass2);
+            const bool sp = (a.c.bucket[u] & BUCKET_SPARSE) != 0;
+            unsigned long long s =
+                du <= 15u ? (sp ? wave_walk<true, true, WK_SPARSE>(a.c, sh, rb, du, a.pass2)
+                                : wave_walk<true, true, WK>(a.c, sh, rb, du, a.pass2))
+                          : (sp ? wave_walk<true, false, WK_SPARSE>(a.c, sh, rb, du, a.pass2)
+                                : wave_walk<true, false, WK>(a.c, sh, rb, du, a.pass2));
             if (a.pass2) {
                 for (uint32_t j = threadIdx.x; j < du; j += WT) {
                     const uint32_t k = rb + j;
@@ -1568,7 +1591,7 @@ static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark,
         if (g > 8192) g = 8192;
         k_work<<<g, 256, 0, s>>>(p.offA, p.adjA, p.xA, p.offB, p.adjB, p.nA, all_ends, mark,
                                  narrow_max,
-                                 hl.small, hl.mid, hl.density, split, w.bucket,
+                                 hl.small, hl.mid, hl.density, HALF_DENSITY, split, w.bucket,
                                  split ? w.nsplit : nullptr,
                                  w.q);
         BFC_HIP(hipGetLastError());
@@ -1587,6 +1610,7 @@ static void fill_args(const Plan &p, const ExactWs &w, CountArgs &a) {
     a.seg1 = w.seg1; a.seg_start = w.seg_start; a.seg_win = w.seg_win;
     a.items = w.items; a.items_wide = w.items_wide; a.items_h1 = w.items_h1;
     a.items_h2 = w.items_h2; a.ovf = w.ovf; a.q = w.q; a.nA = p.nA; a.total = nullptr;
+    a.bucket = w.bucket;
     a.chunk = WCHUNK; a.per_start = nullptr; a.hash_passes = 0;
 }
 
