@@ -941,7 +941,10 @@ __device__ inline uint32_t hpart(uint32_t w, uint32_t P) {
 // HASH_FULL when the table held no free slot for one of them.  Probing runs
 // in rounds: every unresolved entry issues its compare-and-swap in the same
 // round (entries without work hit the thread's zero word, which the swap of
-// 0 for 0 leaves unchanged), so a round costs one LDS round trip; then the
+// 0 for 0 leaves unchanged), so a round costs one LDS round trip; from the
+// second round on, an entry index that no lane of the wave still probes
+// issues nothing (the wave runs as many rounds as its longest probe
+// sequence, and the kernel is bound by instruction issue).  Then the
 // sixteen counter additions go out together.
 template <int S>
 __device__ inline uint32_t hinsert16(uint32_t *key, uint32_t *cnt, uint32_t *zero,
@@ -951,16 +954,24 @@ __device__ inline uint32_t hinsert16(uint32_t *key, uint32_t *cnt, uint32_t *zer
     for (int i = 0; i < 16; i++) h[i] = hslot<S>(w[i]);
     uint32_t pend = on;
     for (int round = 0; pend && round < S; round++) {
+        // after the first round only a few entry indices are still probed
+        // by some lane of the wave: the others issue nothing
+        uint64_t act[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            act[i] = round == 0 ? ~0ull : __builtin_amdgcn_ballot_w64((pend >> i) & 1u);
         uint32_t prev[16];
 #pragma unroll
         for (int i = 0; i < 16; i++) {
             const bool p = (pend >> i) & 1u;
-            prev[i] = atomicCAS(p ? &key[h[i]] : zero, 0u, p ? w[i] + 1u : 0u);
+            prev[i] = 0u;
+            if (act[i]) prev[i] = atomicCAS(p ? &key[h[i]] : zero, 0u, p ? w[i] + 1u : 0u);
         }
 #pragma unroll
         for (int i = 0; i < 16; i++) asm volatile("" : "+v"(prev[i]));
 #pragma unroll
         for (int i = 0; i < 16; i++) {
+            if (!act[i]) continue;
             const bool p = (pend >> i) & 1u;
             const bool done = prev[i] == 0u || prev[i] == w[i] + 1u;
             pend &= ~((uint32_t)(p && done) << i);
