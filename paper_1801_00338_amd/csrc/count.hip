@@ -457,13 +457,27 @@ __device__ inline void wfetch(const uint32_t *adjB, const Piece &pc, uint4 *q) {
     for (int k = 0; k < N; k++) q[k] = *(const uint4 *)(adjB + pc.base + 4 * k);
 }
 
+// Bit i set when entry base + i of an N-entry piece is in the sub-run
+// [lo, lo + len) and is not `skip` (computed once per piece, so that each
+// entry tests one bit).  A piece of a sub-run starts at most three entries
+// before lo and ends inside the run, so 0 <= lo - base < end - base <= N.
+template <bool LOCAL, int N>
+__device__ inline uint32_t piece_bits(const Piece &pc) {
+    const uint32_t a = pc.lo > pc.base ? pc.lo - pc.base : 0u;
+    const uint32_t e = pc.lo + pc.len - pc.base;
+    uint32_t m = pc.len ? ((1u << e) - 1u) & ~((1u << a) - 1u) : 0u;
+    if (LOCAL) {
+        const uint32_t d = pc.skip - pc.base;
+        m &= d < (uint32_t)N ? ~(1u << d) : ~0u;
+    }
+    return m;
+}
+
 // Entry i of the piece -> byte offset of its counter, or of the lane's zero
-// word when it is not in the sub-run.
-__device__ inline uint32_t wslot(const Piece &pc, uint32_t i, uint32_t w, uint32_t wb,
+// word when it is not in the sub-run (bit i of m clear).
+__device__ inline uint32_t wslot(uint32_t m, uint32_t i, uint32_t w, uint32_t wb,
                                  uint32_t zero_byte) {
-    const uint32_t pos = pc.base + i;
-    const bool on = (pos - pc.lo) < pc.len && pos != pc.skip;
-    return on ? w - wb : zero_byte;
+    return (m >> i) & 1u ? w - wb : zero_byte;
 }
 
 // Add one to every counter of the piece; the counters' previous values are
@@ -474,18 +488,21 @@ __device__ inline uint32_t wslot(const Piece &pc, uint32_t i, uint32_t w, uint32
 template <bool LOCAL, bool NIB = false, int K = WK>
 __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
     constexpr uint32_t PER = NIB ? 8 : 4, LOGP = NIB ? 3 : 2, BITS = NIB ? 4 : 8;
-    constexpr uint32_t MASK = (1u << BITS) - 1;
     const uint32_t zb = (WTBL_WORDS + threadIdx.x) * PER;
+    const uint32_t m = piece_bits<LOCAL, 4 * K>(pc);
     uint32_t old[4 * K], sft[4 * K];
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            const uint32_t b = wslot(pc, 4 * k + i, w[i], wb, zb);
-            const uint32_t sb = (b & (PER - 1)) * BITS;
+            const bool on = (m >> (4 * k + i)) & 1u;
+            const uint32_t b = on ? w[i] - wb : zb;
+            // the counter's bit offset, (b mod PER) * BITS, is the low five
+            // bits of b * BITS: shifts and field extracts read only those
+            const uint32_t sb = b * BITS;
             sft[4 * k + i] = sb;
-            old[4 * k + i] = atomicAdd(&sh.tbl[b >> LOGP], (uint32_t)(b != zb) << sb);
+            old[4 * k + i] = atomicAdd(&sh.tbl[b >> LOGP], on ? 1u << (sb & 31u) : 0u);
         }
     }
     // Keep the extraction below the sixteen atomics so that they are all in
@@ -495,7 +512,7 @@ __device__ inline uint32_t wbump(WShared<LOCAL> &sh, const Piece &pc, const uint
     for (int k = 0; k < 4 * K; k++) asm volatile("" : "+v"(old[k]));
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < 4 * K; k++) s += (old[k] >> sft[k]) & MASK;
+    for (int k = 0; k < 4 * K; k++) s += __builtin_amdgcn_ubfe(old[k], sft[k], BITS);
     return s;
 }
 
@@ -505,13 +522,14 @@ __device__ inline uint32_t wread(const WShared<LOCAL> &sh, const Piece &pc, cons
                                  uint32_t wb) {
     const uint8_t *t8 = (const uint8_t *)sh.tbl;
     const uint32_t zb = (WTBL_WORDS + threadIdx.x) * (NIB ? 8 : 4);
+    const uint32_t m = piece_bits<LOCAL, 4 * K>(pc);
     uint32_t v[4 * K];
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            const uint32_t b = wslot(pc, 4 * k + i, w[i], wb, zb);
+            const uint32_t b = wslot(m, 4 * k + i, w[i], wb, zb);
             v[4 * k + i] = NIB ? (sh.tbl[b >> 3] >> ((b & 7u) * 4)) & 0xFu : t8[b];
         }
     }
@@ -527,12 +545,13 @@ template <bool LOCAL, bool NIB = false, int K = WK>
 __device__ inline void wclear(WShared<LOCAL> &sh, const Piece &pc, const uint4 *q, uint32_t wb) {
     uint8_t *t8 = (uint8_t *)sh.tbl;
     const uint32_t zb = (WTBL_WORDS + threadIdx.x) * (NIB ? 8 : 4);
+    const uint32_t m = piece_bits<LOCAL, 4 * K>(pc);
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            const uint32_t b = wslot(pc, 4 * k + i, w[i], wb, zb);
+            const uint32_t b = wslot(m, 4 * k + i, w[i], wb, zb);
             if (NIB) atomicAnd(&sh.tbl[b >> 3], ~(0xFu << ((b & 7u) * 4)));
             else t8[b] = 0;
         }
