@@ -918,7 +918,7 @@ __global__ __launch_bounds__(WT) void k_local_narrow(LocalArgs a) {
 // nearly empty windows, each a round trip of the window walk.  Such a start
 // keeps C_u[w] in an LDS hash table instead and walks its midpoints' whole
 // suffixes in one pass: key w + 1 (0 = empty) placed by multiplicative
-// hashing with linear probing, a byte counter beside it (C_u[w] <= d_u <=
+// hashing with double hashing, a byte counter beside it (C_u[w] <= d_u <=
 // 255).  A compare-and-swap claims or finds the key, and the counter's old
 // value is what the pair {u, w} gains, as in the window walk.  A start with
 // more wedges than half the table takes several passes, each over the end
@@ -948,6 +948,16 @@ template <int S>
 __device__ inline uint32_t hslot(uint32_t w) {
     constexpr int LOG = __builtin_ctz(S);
     return (w * 0x9E3779B1u) >> (32 - LOG);
+}
+
+// Probe step of w (double hashing): odd, so that the S probes of a key
+// visit every slot of the power-of-two table once.  Double hashing keeps
+// the longest probe sequence of a wave's entries (which the wave waits for)
+// shorter than linear probing's clusters do.
+template <int S>
+__device__ inline uint32_t hstep(uint32_t w) {
+    constexpr int LOG = __builtin_ctz(S);
+    return ((w * 0xC2B2AE35u) >> (32 - LOG)) | 1u;
 }
 
 // Partition of w among P passes (independent of the slot bits).
@@ -994,7 +1004,7 @@ __device__ inline uint32_t hinsert16(uint32_t *key, uint32_t *cnt, uint32_t *zer
             const bool p = (pend >> i) & 1u;
             const bool done = prev[i] == 0u || prev[i] == w[i] + 1u;
             pend &= ~((uint32_t)(p && done) << i);
-            h[i] = (p && !done) ? ((h[i] + 1u) & (uint32_t)(S - 1)) : h[i];
+            h[i] = (p && !done) ? ((h[i] + hstep<S>(w[i])) & (uint32_t)(S - 1)) : h[i];
         }
     }
     if (pend) return HASH_FULL;
@@ -1157,7 +1167,7 @@ __device__ void exact_hash(const CountArgs &a, const uint32_t *items, uint32_t c
     finish_launch(a.q, cls, acc, nullptr);
 }
 
-__global__ __launch_bounds__(64) void k_exact_hash_small(CountArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_exact_hash_small(CountArgs a) {
     exact_hash<1, HS_SLOTS>(a, a.items_h1, CLS_HASH1);
 }
 
