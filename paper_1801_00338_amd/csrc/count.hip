@@ -1186,6 +1186,9 @@ __global__ __launch_bounds__(256) void k_exact_hash_mid(CountArgs a) {
 // keeps each midpoint's sub-run of the window to read the final counts back
 // in a second pass.
 constexpr int NWAVES = NT / WT;
+// register cursors per thread in the wide walks (starts of at most WIDE_RC * NT
+// midpoints; local counts hold more state per cursor)
+constexpr int WIDE_RC = 2, WIDE_RC_L = 1;
 constexpr int TBL_WORDS_L = 1 << 14;   // local counts: 64 KiB table, two workgroups per CU
 
 template <int TW>
@@ -1320,20 +1323,40 @@ __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass,
 // A table window covers 2^LOGW consecutive segment windows (2^(G_SHIFT +
 // LOGW) ranks); each midpoint's sub-run of a table window is the union of
 // its (contiguous) segments there, at most 2^LOGW of them.
-template <bool LOCAL, int TW, int HALF, int LOGW>
+// Thread tid walks midpoints tid, tid + NT, ... (wave wv's chunks of 64
+// start at wv * 64 + c * NT).  With RC > 0 (a start of at most RC * NT
+// midpoints) each thread keeps the cursors of its RC midpoints in registers;
+// otherwise they live in the workspace and are loaded and stored back once
+// per window.
+template <bool LOCAL, int TW, int HALF, int LOGW, int RC = 0>
 __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uint32_t rb,
                                         uint32_t du, const WideScratch &ws, bool pass2,
                                         uint32_t kw_lo = 0, uint32_t kw_hi = INF) {
     static_assert((HALF ? 2 : 1) * TW == (1 << (G_SHIFT + LOGW)), "table covers one window");
+    constexpr int R = RC > 0 ? RC : 1;
     const uint32_t tid = threadIdx.x, lane = tid & (WT - 1), wv = tid / WT;
     unsigned long long sum = 0;
     uint32_t mn = INF;
-    for (uint32_t j = tid; j < du; j += NT) {
+    // register cursors (RC > 0): position, segment, its window and end, list end
+    uint32_t cp[R], cs[R], csw[R], cse[R], cev[R], clo[R], chi[R];
+    unsigned long long ces[R];
+#pragma unroll
+    for (int c = 0; c < R; c++) {
+        cp[c] = cs[c] = cse[c] = cev[c] = clo[c] = chi[c] = 0;
+        csw[c] = INF;
+        ces[c] = 0;
+    }
+    // first cursor of midpoint j: returns p, s, sw, se, ev
+    auto start = [&](uint32_t j, uint32_t &p, uint32_t &s, uint32_t &sw, uint32_t &se,
+                     uint32_t &ev) {
         const uint32_t k = rb + j;
-        const uint64_t x = ws.at(j, k);
         const uint32_t v = a.adjA[k];
-        const uint32_t pb = a.offB[v], ev = a.offB[v + 1];
-        uint32_t p = LOCAL ? pb : a.xA[k] + 1, s = 0, sw = INF, se = 0;
+        const uint32_t pb = a.offB[v];
+        ev = a.offB[v + 1];
+        p = LOCAL ? pb : a.xA[k] + 1;
+        s = 0;
+        sw = INF;
+        se = 0;
         // windows [kw_lo, kw_hi) only: the cursor starts at the first entry
         // of window kw_lo or later
         if (kw_lo && p < ev) p = lower_bound_glb(a.adjB, p, ev, kw_lo << (G_SHIFT + LOGW));
@@ -1345,78 +1368,144 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
         } else {
             p = ev;                             // nothing to walk
         }
-        ws.pos[x] = p;
-        ws.seg[x] = s;
-        ws.lim[x] = ev;
-        ws.sw[x] = sw;
-        ws.se[x] = se;
-        if (LOCAL) ws.esum[x] = 0;
+    };
+    // sub-run [lo, hi) of window kw and the cursor moved past it
+    auto advance = [&](uint32_t kw, uint32_t &p, uint32_t &s, uint32_t &sw, uint32_t &se,
+                       uint32_t ev, uint32_t &lo, uint32_t &hi, bool &moved) {
+        lo = hi = 0;
+        moved = false;
+        if (p < ev && (sw >> LOGW) == kw) {
+            lo = p;
+            uint32_t e = se, nsw = INF, nse = 0;
+            s++;
+            if (e < ev) {
+                nsw = a.seg_win[s];
+                nse = a.seg_start[s + 1];
+            }
+            while (e < ev && (nsw >> LOGW) == kw) {
+                e = nse;
+                s++;
+                if (e < ev) {
+                    nsw = a.seg_win[s];
+                    nse = a.seg_start[s + 1];
+                }
+            }
+            hi = e < ev ? e : ev;
+            p = hi;
+            sw = p < ev ? nsw : INF;
+            se = nse;
+            moved = true;
+        }
+    };
+    if (RC > 0) {
+#pragma unroll
+        for (int c = 0; c < R; c++) {
+            const uint32_t j = tid + c * NT;
+            if (j < du) start(j, cp[c], cs[c], csw[c], cse[c], cev[c]);
+        }
+    } else {
+        for (uint32_t j = tid; j < du; j += NT) {
+            const uint64_t x = ws.at(j, rb + j);
+            uint32_t p, s, sw, se, ev;
+            start(j, p, s, sw, se, ev);
+            ws.pos[x] = p;
+            ws.seg[x] = s;
+            ws.lim[x] = ev;
+            ws.sw[x] = sw;
+            ws.se[x] = se;
+            if (LOCAL) ws.esum[x] = 0;
+        }
     }
     uint32_t kw = block_min<NT>(mn, sh.red);
     while (kw < kw_hi) {                        // INF >= kw_hi: no window left
         const uint32_t wb = kw << (G_SHIFT + LOGW);
         uint32_t next = INF;
-        for (uint32_t cb = wv * WT; cb < du; cb += NT) {
-            const uint32_t j = cb + lane, k = rb + j;
-            const uint64_t x = ws.at(j, k);
-            uint32_t lo = 0, hi = 0, skip = INF;
-            if (j < du) {
-                // the cursor in one round of independent loads
-                const uint32_t ev = ws.lim[x];
-                uint32_t p = ws.pos[x], s = ws.seg[x], sw = ws.sw[x];
-                if (p < ev && (sw >> LOGW) == kw) {
-                    lo = p;
-                    uint32_t e = ws.se[x], nsw = INF, nse = 0;
-                    s++;
-                    if (e < ev) {
-                        nsw = a.seg_win[s];
-                        nse = a.seg_start[s + 1];
+        if (RC > 0) {
+#pragma unroll
+            for (int c = 0; c < R; c++) {
+                if (wv * WT + c * NT >= du) break;      // wave-uniform
+                const uint32_t j = tid + c * NT;
+                uint32_t lo = 0, hi = 0, skip = INF;
+                if (j < du) {
+                    bool moved;
+                    advance(kw, cp[c], cs[c], csw[c], cse[c], cev[c], lo, hi, moved);
+                    if (cp[c] < cev[c]) next = min(next, csw[c] >> LOGW);
+                    if (LOCAL) {
+                        skip = a.xA[rb + j];
+                        clo[c] = lo;
+                        chi[c] = hi;
                     }
-                    while (e < ev && (nsw >> LOGW) == kw) {
-                        e = nse;
-                        s++;
-                        if (e < ev) {
-                            nsw = a.seg_win[s];
-                            nse = a.seg_start[s + 1];
-                        }
-                    }
-                    hi = e < ev ? e : ev;
-                    p = hi;
-                    sw = p < ev ? nsw : INF;
-                    ws.pos[x] = p;
-                    ws.seg[x] = s;
-                    ws.sw[x] = sw;
-                    ws.se[x] = nse;
                 }
-                if (p < ev) next = min(next, sw >> LOGW);
-                if (LOCAL) {
-                    skip = a.xA[k];
-                    ws.lo[x] = lo;
-                    ws.hi[x] = hi;
-                }
+                unsigned long long unused;
+                chunk_walk<TW, HALF>(a, sh, 0, lo, hi, skip, wb, sum, unused);
             }
-            unsigned long long unused;
-            chunk_walk<TW, HALF>(a, sh, 0, lo, hi, skip, wb, sum, unused);
-        }
-        if (LOCAL && pass2) {
-            __syncthreads();                    // all counts of the window are final
+        } else {
             for (uint32_t cb = wv * WT; cb < du; cb += NT) {
                 const uint32_t j = cb + lane, k = rb + j;
                 const uint64_t x = ws.at(j, k);
                 uint32_t lo = 0, hi = 0, skip = INF;
                 if (j < du) {
-                    lo = ws.lo[x];
-                    hi = ws.hi[x];
-                    skip = a.xA[k];
+                    // the cursor in one round of independent loads
+                    const uint32_t ev = ws.lim[x];
+                    uint32_t p = ws.pos[x], s = ws.seg[x], sw = ws.sw[x], se = ws.se[x];
+                    bool moved;
+                    advance(kw, p, s, sw, se, ev, lo, hi, moved);
+                    if (moved) {
+                        ws.pos[x] = p;
+                        ws.seg[x] = s;
+                        ws.sw[x] = sw;
+                        ws.se[x] = se;
+                    }
+                    if (p < ev) next = min(next, sw >> LOGW);
+                    if (LOCAL) {
+                        skip = a.xA[k];
+                        ws.lo[x] = lo;
+                        ws.hi[x] = hi;
+                    }
                 }
-                unsigned long long e = 0;
-                chunk_walk<TW, HALF>(a, sh, 1, lo, hi, skip, wb, sum, e);
-                if (j < du && e) ws.esum[x] += e;
+                unsigned long long unused;
+                chunk_walk<TW, HALF>(a, sh, 0, lo, hi, skip, wb, sum, unused);
+            }
+        }
+        if (LOCAL && pass2) {
+            __syncthreads();                    // all counts of the window are final
+            if (RC > 0) {
+#pragma unroll
+                for (int c = 0; c < R; c++) {
+                    if (wv * WT + c * NT >= du) break;
+                    const uint32_t j = tid + c * NT;
+                    const bool in = j < du;
+                    unsigned long long e = 0;
+                    chunk_walk<TW, HALF>(a, sh, 1, in ? clo[c] : 0u, in ? chi[c] : 0u,
+                                         in ? a.xA[rb + j] : INF, wb, sum, e);
+                    ces[c] += in ? e : 0ull;
+                }
+            } else {
+                for (uint32_t cb = wv * WT; cb < du; cb += NT) {
+                    const uint32_t j = cb + lane, k = rb + j;
+                    const uint64_t x = ws.at(j, k);
+                    uint32_t lo = 0, hi = 0, skip = INF;
+                    if (j < du) {
+                        lo = ws.lo[x];
+                        hi = ws.hi[x];
+                        skip = a.xA[k];
+                    }
+                    unsigned long long e = 0;
+                    chunk_walk<TW, HALF>(a, sh, 1, lo, hi, skip, wb, sum, e);
+                    if (j < du && e) ws.esum[x] += e;
+                }
             }
         }
         __syncthreads();
         clear_table(sh);
         kw = block_min<NT>(next, sh.red);
+    }
+    if (LOCAL && RC > 0) {
+#pragma unroll
+        for (int c = 0; c < R; c++) {
+            const uint32_t j = tid + c * NT;
+            if (j < du) ws.esum[ws.at(j, rb + j)] = ces[c];
+        }
     }
     return sum;
 }
@@ -1441,8 +1530,9 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
         const uint32_t du = a.offA[u + 1] - rb;
         // 16-bit counters over two segment windows when C_u[w] <= d_u fits
         const unsigned long long s =
-            du <= 0xFFFFu ? walk_wide<false, TBL_WORDS, 1, 1>(a, sh, rb, du, ws, false)
-                          : walk_wide<false, TBL_WORDS, 0, 0>(a, sh, rb, du, ws, false);
+            du <= WIDE_RC * NT ? walk_wide<false, TBL_WORDS, 1, 1, WIDE_RC>(a, sh, rb, du, ws, false)
+            : du <= 0xFFFFu    ? walk_wide<false, TBL_WORDS, 1, 1>(a, sh, rb, du, ws, false)
+                               : walk_wide<false, TBL_WORDS, 0, 0>(a, sh, rb, du, ws, false);
         if (a.per_start) {
             const unsigned long long t = block_sum64<NT>(s, sh.red64);
             if (threadIdx.x == 0) a.per_start[u] = t;
@@ -1456,7 +1546,8 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
 // Local counts of wide starts: 16-bit counters over windows of 2^15 ranks
 // when d_u <= 65535 (two segment windows per table), else 32-bit counters
 // over 2^14.
-__global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a, WideScratch ws) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_local_wide(LocalArgs a,
+                                                                                   WideScratch ws) {
     __shared__ SharedT<TBL_WORDS_L> sh;
     __shared__ uint32_t last;
     clear_table(sh);
@@ -1472,7 +1563,10 @@ __global__ __launch_bounds__(NT) void k_local_wide(LocalArgs a, WideScratch ws) 
         const uint32_t kw_lo = (uint32_t)((uint64_t)g * nwin / G);
         const uint32_t kw_hi = g + 1 == G ? INF : (uint32_t)((uint64_t)(g + 1) * nwin / G);
         unsigned long long s =
-            du <= 0xFFFFu
+            du <= WIDE_RC_L * NT
+                ? walk_wide<true, TBL_WORDS_L, 1, 1, WIDE_RC_L>(a.c, sh, rb, du, ws, a.pass2, kw_lo,
+                                                                kw_hi)
+            : du <= 0xFFFFu
                 ? walk_wide<true, TBL_WORDS_L, 1, 1>(a.c, sh, rb, du, ws, a.pass2, kw_lo, kw_hi)
                 : walk_wide<true, TBL_WORDS_L, 0, 0>(a.c, sh, rb, du, ws, a.pass2, kw_lo, kw_hi);
         __syncthreads();
