@@ -1181,10 +1181,11 @@ __global__ __launch_bounds__(256) void k_exact_hash_mid(CountArgs a) {
 // midpoints are split into chunks of 64; wave w takes chunks w, w + 8, ...
 // and, like the narrow walk, cuts their sub-runs into 16-entry pieces with a
 // wave prefix sum, so a window needs workgroup barriers only at its end.
-// Each midpoint's cursor (position, segment) lives in the workspace at the
-// start's adjacency position; windows no suffix touches are skipped.  LOCAL
-// keeps each midpoint's sub-run of the window to read the final counts back
-// in a second pass.
+// Each midpoint's cursor (position, segment) lives in registers (starts of
+// few midpoints) or in the workspace at the start's adjacency position;
+// windows no suffix touches are skipped, and a midpoint without entries in
+// a window costs one load there.  LOCAL keeps each midpoint's sub-run of the
+// window to read the final counts back in a second pass.
 constexpr int NWAVES = NT / WT;
 // register cursors per thread in the wide walks (starts of at most WIDE_RC * NT
 // midpoints; local counts hold more state per cursor)
@@ -1403,18 +1404,32 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
             const uint32_t j = tid + c * NT;
             if (j < du) start(j, cp[c], cs[c], csw[c], cse[c], cev[c]);
         }
-    } else {
+    }
+    // workspace cursors: a start whose remaining entries are fewer than its
+    // (midpoint, window) pairs ("lazy") loads a cursor's other fields only
+    // when its segment window is the current one; a dense start loads them
+    // all in one round
+    bool lazy = false;
+    if (RC == 0) {
+        unsigned long long rem = 0;
         for (uint32_t j = tid; j < du; j += NT) {
             const uint64_t x = ws.at(j, rb + j);
             uint32_t p, s, sw, se, ev;
             start(j, p, s, sw, se, ev);
+            rem += ev - p;
             ws.pos[x] = p;
             ws.seg[x] = s;
             ws.lim[x] = ev;
             ws.sw[x] = sw;
             ws.se[x] = se;
-            if (LOCAL) ws.esum[x] = 0;
+            if (LOCAL) {
+                ws.lo[x] = ws.hi[x] = 0;
+                ws.esum[x] = 0;
+            }
         }
+        rem = block_sum64<NT>(rem, sh.red64);
+        const uint64_t nwin = ((uint64_t)(a.nA - 1) >> (G_SHIFT + LOGW)) + 1;
+        lazy = rem < (uint64_t)du * (nwin - (kw_lo < nwin ? kw_lo : 0));
     }
     uint32_t kw = block_min<NT>(mn, sh.red);
     while (kw < kw_hi) {                        // INF >= kw_hi: no window left
@@ -1445,23 +1460,39 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                 const uint64_t x = ws.at(j, k);
                 uint32_t lo = 0, hi = 0, skip = INF;
                 if (j < du) {
-                    // the cursor in one round of independent loads
-                    const uint32_t ev = ws.lim[x];
-                    uint32_t p = ws.pos[x], s = ws.seg[x], sw = ws.sw[x], se = ws.se[x];
-                    bool moved;
-                    advance(kw, p, s, sw, se, ev, lo, hi, moved);
-                    if (moved) {
+                    // lazy: a midpoint without entries in this window costs
+                    // one load (its segment window; INF once its list is
+                    // done); else the cursor in one round of independent loads
+                    uint32_t ev = 0, p = 0, s = 0, se = 0;
+                    if (!lazy) {
+                        ev = ws.lim[x];
+                        p = ws.pos[x];
+                        s = ws.seg[x];
+                        se = ws.se[x];
+                    }
+                    uint32_t sw = ws.sw[x];
+                    if ((sw >> LOGW) == kw) {
+                        if (lazy) {
+                            ev = ws.lim[x];
+                            p = ws.pos[x];
+                            s = ws.seg[x];
+                            se = ws.se[x];
+                        }
+                        bool moved;
+                        advance(kw, p, s, sw, se, ev, lo, hi, moved);
                         ws.pos[x] = p;
                         ws.seg[x] = s;
                         ws.sw[x] = sw;
                         ws.se[x] = se;
+                        if (LOCAL) skip = a.xA[k];
                     }
-                    if (p < ev) next = min(next, sw >> LOGW);
-                    if (LOCAL) {
-                        skip = a.xA[k];
+                    // the window's sub-run for the second look (lazy: only
+                    // a nonempty one, which the second look empties again)
+                    if (LOCAL && (!lazy || hi > lo)) {
                         ws.lo[x] = lo;
                         ws.hi[x] = hi;
                     }
+                    if (sw != INF) next = min(next, sw >> LOGW);     // INF: list done
                 }
                 unsigned long long unused;
                 chunk_walk<TW, HALF>(a, sh, 0, lo, hi, skip, wb, sum, unused);
@@ -1488,7 +1519,10 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                     if (j < du) {
                         lo = ws.lo[x];
                         hi = ws.hi[x];
-                        skip = a.xA[k];
+                        if (hi > lo) {
+                            skip = a.xA[k];
+                            if (lazy) ws.hi[x] = lo;
+                        }
                     }
                     unsigned long long e = 0;
                     chunk_walk<TW, HALF>(a, sh, 1, lo, hi, skip, wb, sum, e);
