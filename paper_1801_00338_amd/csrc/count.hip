@@ -1213,18 +1213,18 @@ __device__ inline void clear_table(SharedT<TW> &sh) {
 // pass 0: add one to the counters of the piece's entries, return the sum of
 // previous values; pass 1: return the sum of the final counters.  HALF: two
 // 16-bit counters per word (C_u[w] <= d_u <= 65535), else 32-bit counters.
-template <int TW, int HALF>
+template <int TW, int HALF, int K = WK>
 __device__ inline uint32_t cpiece_walk(SharedT<TW> &sh, int pass, const Piece &pc,
                                        const uint4 *q, uint32_t wb) {
     const uint32_t zw = TW + threadIdx.x;
-    uint32_t v[4 * WK];
+    const uint32_t m = piece_bits<true, 4 * K>(pc);
+    uint32_t v[4 * K];
 #pragma unroll
-    for (int k = 0; k < WK; k++) {
+    for (int k = 0; k < K; k++) {
         const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            const uint32_t pos = pc.base + 4 * k + i;
-            const bool on = (pos - pc.lo) < pc.len && pos != pc.skip;
+            const bool on = (m >> (4 * k + i)) & 1u;
             const uint32_t rel = w[i] - wb;
             if (HALF) {
                 const uint32_t word = on ? rel >> 1 : zw;
@@ -1238,12 +1238,12 @@ __device__ inline uint32_t cpiece_walk(SharedT<TW> &sh, int pass, const Piece &p
             }
         }
     }
-    // all sixteen LDS operations in flight before the first result is used
+    // all the piece's LDS operations in flight before the first result is used
 #pragma unroll
-    for (int k = 0; k < 4 * WK; k++) asm volatile("" : "+v"(v[k]));
+    for (int k = 0; k < 4 * K; k++) asm volatile("" : "+v"(v[k]));
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < 4 * WK; k++) s += v[k];
+    for (int k = 0; k < 4 * K; k++) s += v[k];
     return s;
 }
 
@@ -1253,12 +1253,12 @@ __device__ inline uint32_t cpiece_walk(SharedT<TW> &sh, int pass, const Piece &p
 // the one carried over), and the next round's pieces are loaded while this
 // round's counters are updated (unrolled twice so the buffers swap without
 // copies).
-template <int TW, int HALF>
+template <int TW, int HALF, int K>
 __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass, uint32_t lo,
                                   uint32_t hi, uint32_t skip, uint32_t wb,
                                   unsigned long long &sum, unsigned long long &esum_mid) {
     const uint32_t lane = threadIdx.x & (WT - 1), wv = threadIdx.x / WT;
-    const uint32_t np = hi > lo ? (((hi + 3) >> 2) - (lo >> 2) + WK - 1) / WK : 0;
+    const uint32_t np = hi > lo ? (((hi + 3) >> 2) - (lo >> 2) + K - 1) / K : 0;
     const uint32_t inc = wave_incl_scan(np);
     const uint32_t NP = wave_last(inc);
     const uint32_t first = inc - np;
@@ -1287,8 +1287,8 @@ __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass,
         const bool valid = pi < NP;
         Piece pc;
         const uint32_t plo = sh.lo[wv][j], phi = sh.hi[wv][j];
-        const uint32_t g0 = (plo >> 2) + (pi - sh.pre[wv][j]) * WK;
-        const uint32_t end = min(phi, (g0 + WK) << 2);
+        const uint32_t g0 = (plo >> 2) + (pi - sh.pre[wv][j]) * K;
+        const uint32_t end = min(phi, (g0 + K) << 2);
         pc.base = valid ? g0 << 2 : 0;
         pc.lo = plo;
         pc.len = valid ? end - plo : 0;
@@ -1298,20 +1298,20 @@ __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass,
     };
     uint32_t part = 0;
     auto work = [&](const Piece &pc, const uint4 *q) {
-        const uint32_t s = cpiece_walk<TW, HALF>(sh, pass, pc, q, wb);
+        const uint32_t s = cpiece_walk<TW, HALF, K>(sh, pass, pc, q, wb);
         if (pass == 0) part += s;
         else if (s) atomicAdd(&sh.esum[wv][pc.j], s);
     };
     Piece p0 = map_round(0);
-    uint4 q0[WK], q1[WK];
-    wfetch<WK>(a.adjB, p0, q0);
+    uint4 q0[K], q1[K];
+    wfetch<K>(a.adjB, p0, q0);
     for (uint32_t r = 0;; r += 2) {
         Piece p1 = map_round(r + 1);
-        wfetch<WK>(a.adjB, p1, q1);
+        wfetch<K>(a.adjB, p1, q1);
         work(p0, q0);
         if (r + 1 >= rounds) break;
         p0 = map_round(r + 2);
-        wfetch<WK>(a.adjB, p0, q0);
+        wfetch<K>(a.adjB, p0, q0);
         work(p1, q1);
         if (r + 2 >= rounds) break;
     }
@@ -1329,7 +1329,7 @@ __device__ inline void chunk_walk(const CountArgs &a, SharedT<TW> &sh, int pass,
 // midpoints) each thread keeps the cursors of its RC midpoints in registers;
 // otherwise they live in the workspace and are loaded and stored back once
 // per window.
-template <bool LOCAL, int TW, int HALF, int LOGW, int RC = 0>
+template <bool LOCAL, int TW, int HALF, int LOGW, int RC = 0, int K = WK>
 __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uint32_t rb,
                                         uint32_t du, const WideScratch &ws, bool pass2,
                                         uint32_t kw_lo = 0, uint32_t kw_hi = INF) {
@@ -1452,7 +1452,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                     }
                 }
                 unsigned long long unused;
-                chunk_walk<TW, HALF>(a, sh, 0, lo, hi, skip, wb, sum, unused);
+                chunk_walk<TW, HALF, K>(a, sh, 0, lo, hi, skip, wb, sum, unused);
             }
         } else {
             for (uint32_t cb = wv * WT; cb < du; cb += NT) {
@@ -1495,7 +1495,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                     if (sw != INF) next = min(next, sw >> LOGW);     // INF: list done
                 }
                 unsigned long long unused;
-                chunk_walk<TW, HALF>(a, sh, 0, lo, hi, skip, wb, sum, unused);
+                chunk_walk<TW, HALF, K>(a, sh, 0, lo, hi, skip, wb, sum, unused);
             }
         }
         if (LOCAL && pass2) {
@@ -1507,7 +1507,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                     const uint32_t j = tid + c * NT;
                     const bool in = j < du;
                     unsigned long long e = 0;
-                    chunk_walk<TW, HALF>(a, sh, 1, in ? clo[c] : 0u, in ? chi[c] : 0u,
+                    chunk_walk<TW, HALF, K>(a, sh, 1, in ? clo[c] : 0u, in ? chi[c] : 0u,
                                          in ? a.xA[rb + j] : INF, wb, sum, e);
                     ces[c] += in ? e : 0ull;
                 }
@@ -1525,7 +1525,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                         }
                     }
                     unsigned long long e = 0;
-                    chunk_walk<TW, HALF>(a, sh, 1, lo, hi, skip, wb, sum, e);
+                    chunk_walk<TW, HALF, K>(a, sh, 1, lo, hi, skip, wb, sum, e);
                     if (j < du && e) ws.esum[x] += e;
                 }
             }
@@ -1542,6 +1542,16 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
         }
     }
     return sum;
+}
+
+// A wide start whose wedges (below 2^b, b the plan's bucket) are at most its
+// (midpoint, table window) pairs over the windows it walks (from rank lo)
+// has sub-runs of about one entry: its pieces are WK_WIDE_SPARSE groups.
+constexpr int WK_WIDE_SPARSE = 1;
+__device__ inline bool wide_sparse(uint16_t bucket, uint32_t du, uint32_t nA, uint32_t lo) {
+    const uint32_t b = bucket & 255u, logw = du <= 0xFFFFu ? 1u : 0u;
+    const uint64_t nwin = ((uint64_t)(nA - 1) >> (G_SHIFT + logw)) + 1 - (lo >> (G_SHIFT + logw));
+    return b < 63 && (1ull << b) <= (uint64_t)du * nwin;
 }
 
 template <int TW>
@@ -1563,10 +1573,16 @@ __global__ __launch_bounds__(NT) void k_exact_wide(CountArgs a, WideScratch ws) 
         const uint32_t rb = a.offA[u];
         const uint32_t du = a.offA[u + 1] - rb;
         // 16-bit counters over two segment windows when C_u[w] <= d_u fits
+        const bool sp = wide_sparse(a.bucket[u], du, a.nA, u);
         const unsigned long long s =
-            du <= WIDE_RC * NT ? walk_wide<false, TBL_WORDS, 1, 1, WIDE_RC>(a, sh, rb, du, ws, false)
-            : du <= 0xFFFFu    ? walk_wide<false, TBL_WORDS, 1, 1>(a, sh, rb, du, ws, false)
-                               : walk_wide<false, TBL_WORDS, 0, 0>(a, sh, rb, du, ws, false);
+            du <= WIDE_RC * NT
+                ? (sp ? walk_wide<false, TBL_WORDS, 1, 1, WIDE_RC, WK_WIDE_SPARSE>(a, sh, rb, du, ws,
+                                                                                   false)
+                      : walk_wide<false, TBL_WORDS, 1, 1, WIDE_RC>(a, sh, rb, du, ws, false))
+            : du <= 0xFFFFu
+                ? (sp ? walk_wide<false, TBL_WORDS, 1, 1, 0, WK_WIDE_SPARSE>(a, sh, rb, du, ws, false)
+                      : walk_wide<false, TBL_WORDS, 1, 1>(a, sh, rb, du, ws, false))
+                : walk_wide<false, TBL_WORDS, 0, 0>(a, sh, rb, du, ws, false);
         if (a.per_start) {
             const unsigned long long t = block_sum64<NT>(s, sh.red64);
             if (threadIdx.x == 0) a.per_start[u] = t;
@@ -1596,12 +1612,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const uint32_t nwin = ((a.c.nA - 1) >> (G_SHIFT + logw)) + 1;
         const uint32_t kw_lo = (uint32_t)((uint64_t)g * nwin / G);
         const uint32_t kw_hi = g + 1 == G ? INF : (uint32_t)((uint64_t)(g + 1) * nwin / G);
+        const bool sp = wide_sparse(a.c.bucket[u], du, a.c.nA, 0);
         unsigned long long s =
             du <= WIDE_RC_L * NT
-                ? walk_wide<true, TBL_WORDS_L, 1, 1, WIDE_RC_L>(a.c, sh, rb, du, ws, a.pass2, kw_lo,
-                                                                kw_hi)
+                ? (sp ? walk_wide<true, TBL_WORDS_L, 1, 1, WIDE_RC_L, WK_WIDE_SPARSE>(
+                            a.c, sh, rb, du, ws, a.pass2, kw_lo, kw_hi)
+                      : walk_wide<true, TBL_WORDS_L, 1, 1, WIDE_RC_L>(a.c, sh, rb, du, ws, a.pass2,
+                                                                      kw_lo, kw_hi))
             : du <= 0xFFFFu
-                ? walk_wide<true, TBL_WORDS_L, 1, 1>(a.c, sh, rb, du, ws, a.pass2, kw_lo, kw_hi)
+                ? (sp ? walk_wide<true, TBL_WORDS_L, 1, 1, 0, WK_WIDE_SPARSE>(a.c, sh, rb, du, ws,
+                                                                             a.pass2, kw_lo, kw_hi)
+                      : walk_wide<true, TBL_WORDS_L, 1, 1>(a.c, sh, rb, du, ws, a.pass2, kw_lo,
+                                                           kw_hi))
                 : walk_wide<true, TBL_WORDS_L, 0, 0>(a.c, sh, rb, du, ws, a.pass2, kw_lo, kw_hi);
         __syncthreads();
         s = block_sum64<NT>(s, sh.red64);
