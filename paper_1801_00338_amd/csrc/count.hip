@@ -166,21 +166,20 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
         uint32_t rb = offA[u], re = offA[u + 1];
         if (mark && !mark[u]) re = rb;          // start not asked for
         unsigned long long t = 0;
-        uint32_t top = 0, bot = INF;            // highest and lowest end point rank
+        uint32_t top = 0;                       // highest end point rank
         const bool spans = (hs_max | hm_max | half_density) != 0u;
         for (uint32_t k = rb + lane; k < re; k += WAVE) {
             uint32_t v = adjA[k];
             const uint32_t e = offB[v + 1];
             t += e - (all_ends ? offB[v] : xA[k]) - 1;
-            if (spans) {
-                top = max(top, adjB[e - 1]);
-                if (all_ends) bot = min(bot, adjB[offB[v]]);
-            }
+            if (spans) top = max(top, adjB[e - 1]);
         }
         t = wave_sum64(t);
         top = wave_incl_max(top);
         top = wave_last(top);
-        bot = all_ends ? wave_min(bot) : u;
+        // lowest end point rank: above u for the exact count; the local
+        // counts take all end points, whose span is taken from rank 0
+        const uint32_t bot = all_ends ? 0u : u;
         // a start with one midpoint shares at most one with any w: C_u[w] <= 1
         // adds nothing to a count, so it is not queued (its outputs stay 0)
         if (re - rb < 2) t = 0;

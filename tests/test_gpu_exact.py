@@ -258,3 +258,40 @@ def test_local_counts_with_split_hub_starts(api, case):
     # vertex counts only (no second look at the final counts)
     cl, cr, _ = g.local_split(1, edges=False)
     assert np.array_equal(cl, ol) and np.array_equal(cr, orr)
+
+
+# ------------------------------------------------------------------ sparse hubs on a large side
+def test_sparse_hubs_on_a_large_side(api):
+    """Hub starts whose midpoints have short lists spread over a side of 2M
+    ranks (62 to 123 counter windows): fewer wedges than (midpoint, window)
+    pairs, so the wide walks take one-group pieces, and hubs past the
+    register-cursor limit load a cursor only in the windows where it has
+    entries.  Degrees 300 and 400 (register cursors), 700, 900 and 3,000
+    (workspace cursors, 16-bit table) and 70,000 (32-bit table); whole and
+    split into parts of few windows."""
+    rng = np.random.default_rng(31)
+    nl, nr = 2_000_000, 80_000
+    parts_l, parts_r = [], []
+    for i, d in enumerate((300, 400, 700, 900, 3000, 70_000)):
+        parts_l.append(np.full(d, i * 333_331, np.uint32))
+        parts_r.append(rng.choice(nr, d, replace=False).astype(np.uint32))
+    bl = rng.integers(0, nl, 240_000).astype(np.uint64)
+    br = rng.integers(0, nr, 240_000).astype(np.uint64)
+    key = np.unique(np.concatenate([np.concatenate(parts_l).astype(np.uint64) * nr
+                                    + np.concatenate(parts_r), bl * nr + br]))
+    l = (key // nr).astype(np.uint32)
+    r = (key % nr).astype(np.uint32)
+    print(f"case nl={nl} nr={nr} m={l.size}", flush=True)
+    g = api.Graph(nl, nr, l, r)
+    assert g.side_used() == api.BFC_SIDE_L
+    want = oracle.exact(nl, nr, l, r)[0]
+    for side in (0, 1, 2):
+        assert g.exact(side) == want, side
+    ol, orr = oracle.per_vertex(nl, nr, l, r)
+    oe = oracle.per_edge(nl, nr, l, r)
+    for split in (0, 1, 5000):
+        print(f"split {split}", flush=True)
+        cl, cr, ce = g.local_split(split)
+        assert np.array_equal(cl, ol), split
+        assert np.array_equal(cr, orr), split
+        assert np.array_equal(ce, oe), split
