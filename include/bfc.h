@@ -330,7 +330,7 @@ typedef struct bfc_tuning {
     uint32_t narrow_waves_per_cu; /* narrow grid, waves per compute unit (1..8; 8) */
     uint32_t wide_groups_per_cu;  /* wide grid, workgroups per compute unit (1..2; 2) */
     uint32_t hash_small_max;      /* narrow starts with at most this many wedges use the
-                                     one-wave hash table (1..2048; 2048; BFC_HASH_OFF: none) */
+                                     one-wave hash table (1..2048; 1024; BFC_HASH_OFF: none) */
     uint32_t hash_mid_max;        /* ... else at most this many the four-wave one
                                      (1..16384; 16384; BFC_HASH_OFF: none) */
     uint32_t hash_passes;         /* passes of a hash start over its wedges (1..4; 0: as many
@@ -338,7 +338,7 @@ typedef struct bfc_tuning {
                                      table hands the start to the narrow window walk */
     uint32_t hash_max_density;    /* a start takes a hash table only when it has at most
                                      this many wedges per counter window its end points
-                                     span (64) */
+                                     span (32) */
 } bfc_tuning;
 #define BFC_HASH_OFF 0xFFFFFFFFu
 

@@ -146,7 +146,7 @@ struct QueueState {
 // (bucket bit 15) for the narrow walk's short pieces.
 constexpr uint64_t SPLIT_WEDGES = 1ull << 24;  // local counts: wedges per part of a wide start
 constexpr uint32_t SPLIT_MAX = 4096;
-constexpr uint32_t HASH_DENSITY = 64, HALF_DENSITY = 384;
+constexpr uint32_t HASH_DENSITY = 32, HALF_DENSITY = 384;
 constexpr uint16_t BUCKET_SPARSE = 0x8000;
 __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32_t *adjA,
                                               const uint32_t *xA, const uint32_t *offB,
@@ -930,6 +930,8 @@ constexpr int HS_SLOTS = 1024, HM_SLOTS = 8192;
 constexpr uint32_t HS_CAP = HS_SLOTS / 2, HM_CAP = HM_SLOTS / 2;   // entries per pass
 constexpr uint32_t HASH_PASSES = 4;
 constexpr uint32_t HS_MAX = HASH_PASSES * HS_CAP, HM_MAX = HASH_PASSES * HM_CAP;
+// default wedge limit of the small table (the mid table takes the starts above it)
+constexpr uint32_t HS_DEFAULT = 1024;
 constexpr uint32_t HASH_FULL = 0xFFFFFFFFu;
 
 template <int NW, int S>
@@ -1761,7 +1763,7 @@ static bool overflow_risk(uint64_t wedges, uint32_t max_deg) {
 struct HashLimits {
     uint32_t small, mid, density;
 };
-constexpr HashLimits HASH_DEFAULT = {HS_MAX, HM_MAX, HASH_DENSITY}, HASH_NONE = {0, 0, 0};
+constexpr HashLimits HASH_DEFAULT = {HS_DEFAULT, HM_MAX, HASH_DENSITY}, HASH_NONE = {0, 0, 0};
 
 static int prepare(const Plan &p, ExactWs &w, int all_ends, const uint8_t *mark, hipStream_t s,
                    uint32_t narrow_max = NARROW_MAX, HashLimits hl = HASH_NONE,
@@ -1809,7 +1811,7 @@ static int resolve_tuning(const bfc_tuning *t, bfc_tuning &r) {
     r.chunk = WCHUNK;
     r.narrow_waves_per_cu = 8;
     r.wide_groups_per_cu = 2;
-    r.hash_small_max = HS_MAX;
+    r.hash_small_max = HS_DEFAULT;
     r.hash_mid_max = HM_MAX;
     r.hash_passes = 0;
     r.hash_max_density = HASH_DENSITY;
@@ -2178,8 +2180,8 @@ int bfc_autotune(const bfc_graph *g, uint32_t nparts, const uint32_t *d_part_l,
             }
     }
     {
-        // hash tables for sparse starts: off, or up to 16, 64 or 256 wedges per window
-        const uint32_t hd[] = {0, 16, 64, 256};
+        // hash tables for sparse starts: off, or up to 16, 32, 64 or 256 wedges per window
+        const uint32_t hd[] = {0, 16, 32, 64, 256};
         const bfc_tuning base = cur;
         for (uint32_t d : hd) {
             bfc_tuning t = base;
