@@ -1373,9 +1373,8 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
     };
     // sub-run [lo, hi) of window kw and the cursor moved past it
     auto advance = [&](uint32_t kw, uint32_t &p, uint32_t &s, uint32_t &sw, uint32_t &se,
-                       uint32_t ev, uint32_t &lo, uint32_t &hi, bool &moved) {
+                       uint32_t ev, uint32_t &lo, uint32_t &hi) {
         lo = hi = 0;
-        moved = false;
         if (p < ev && (sw >> LOGW) == kw) {
             lo = p;
             uint32_t e = se, nsw = INF, nse = 0;
@@ -1396,7 +1395,6 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
             p = hi;
             sw = p < ev ? nsw : INF;
             se = nse;
-            moved = true;
         }
     };
     if (RC > 0) {
@@ -1443,8 +1441,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                 const uint32_t j = tid + c * NT;
                 uint32_t lo = 0, hi = 0, skip = INF;
                 if (j < du) {
-                    bool moved;
-                    advance(kw, cp[c], cs[c], csw[c], cse[c], cev[c], lo, hi, moved);
+                    advance(kw, cp[c], cs[c], csw[c], cse[c], cev[c], lo, hi);
                     if (cp[c] < cev[c]) next = min(next, csw[c] >> LOGW);
                     if (LOCAL) {
                         skip = a.xA[rb + j];
@@ -1479,8 +1476,7 @@ __device__ unsigned long long walk_wide(const CountArgs &a, SharedT<TW> &sh, uin
                             s = ws.seg[x];
                             se = ws.se[x];
                         }
-                        bool moved;
-                        advance(kw, p, s, sw, se, ev, lo, hi, moved);
+                        advance(kw, p, s, sw, se, ev, lo, hi);
                         ws.pos[x] = p;
                         ws.seg[x] = s;
                         ws.sw[x] = sw;
