@@ -143,11 +143,12 @@ struct QueueState {
 // hl.density wedges (default HASH_DENSITY) per counter window its end points
 // span (the window walk pays about one round trip per window it touches).
 // A start of at most half_density wedges per spanned window is marked
-// (bucket bit 15) for the narrow walk's short pieces.
+// (bucket bit 15) for the narrow walk's short pieces, one of at most
+// QUARTER_DENSITY (bucket bit 14) for its shortest.
 constexpr uint64_t SPLIT_WEDGES = 1ull << 24;  // local counts: wedges per part of a wide start
 constexpr uint32_t SPLIT_MAX = 4096;
-constexpr uint32_t HASH_DENSITY = 32, HALF_DENSITY = 384;
-constexpr uint16_t BUCKET_SPARSE = 0x8000;
+constexpr uint32_t HASH_DENSITY = 32, HALF_DENSITY = 384, QUARTER_DENSITY = 128;
+constexpr uint16_t BUCKET_SPARSE = 0x8000, BUCKET_SPARSER = 0x4000;
 __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32_t *adjA,
                                               const uint32_t *xA, const uint32_t *offB,
                                               const uint32_t *adjB,
@@ -202,7 +203,9 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t *offA, const uint32
                 gg = gg < SPLIT_MAX ? gg : SPLIT_MAX;
                 G = gg > 1 ? (uint32_t)gg : 1u;
             }
-            bucket[u] = (uint16_t)(b | cls << 8) | (sparse ? BUCKET_SPARSE : 0);
+            const bool sparser = half_density && t <= (uint64_t)QUARTER_DENSITY * span;
+            bucket[u] = (uint16_t)(b | cls << 8) | (sparse ? BUCKET_SPARSE : 0) |
+                        (sparser ? BUCKET_SPARSER : 0);
             if (nsplit) nsplit[u] = (uint16_t)G;
             if (b) atomicAdd(&hist[cls][b], G);
         }
@@ -386,10 +389,11 @@ __device__ inline uint32_t group_mask(uint32_t base, uint32_t lo, uint32_t hi, u
 // entries) of one midpoint; lanes take pieces round-robin, so one search maps
 // a piece to its midpoint and the entries of a piece are contiguous.  The
 // narrow walk of a start whose windows are sparse (few wedges per window its
-// end points span, marked by the plan) cuts pieces of WK_SPARSE groups: a
-// window's work is then spread over more lanes and each lane's counter
-// updates (whose cost does not depend on how many of its entries are in the
-// sub-run) are halved.
+// end points span, marked by the plan) cuts pieces of WK_SPARSE groups, and
+// of one group for the sparsest starts of the exact count: a window's work
+// is then spread over more lanes and each lane's counter updates (whose
+// cost does not depend on how many of its entries are in the sub-run) are
+// halved or quartered.
 constexpr int WK = 4, WK_SPARSE = 2;
 
 template <bool LOCAL>
@@ -864,12 +868,15 @@ __global__ __launch_bounds__(WT) void k_exact_narrow(CountArgs a) {
         b++;
         const uint32_t rb = a.offA[u];
         const uint32_t du = a.offA[u + 1] - rb;
-        const bool sp = (a.bucket[u] & BUCKET_SPARSE) != 0;
+        const uint16_t bk = a.bucket[u];
+        const bool sp = (bk & BUCKET_SPARSE) != 0, sp2 = (bk & BUCKET_SPARSER) != 0;
         const unsigned long long s =
-            du <= 15u ? (sp ? wave_walk<false, true, WK_SPARSE>(a, sh, rb, du, false)
-                            : wave_walk<false, true, WK>(a, sh, rb, du, false))
-                      : (sp ? wave_walk<false, false, WK_SPARSE>(a, sh, rb, du, false)
-                            : wave_walk<false, false, WK>(a, sh, rb, du, false));
+            du <= 15u ? (sp2 ? wave_walk<false, true, 1>(a, sh, rb, du, false)
+                         : sp ? wave_walk<false, true, WK_SPARSE>(a, sh, rb, du, false)
+                              : wave_walk<false, true, WK>(a, sh, rb, du, false))
+                      : (sp2 ? wave_walk<false, false, 1>(a, sh, rb, du, false)
+                         : sp ? wave_walk<false, false, WK_SPARSE>(a, sh, rb, du, false)
+                              : wave_walk<false, false, WK>(a, sh, rb, du, false));
         if (a.per_start) {
             const unsigned long long t = wave_sum64(s);
             if (threadIdx.x == 0) a.per_start[u] = t;
