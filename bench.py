@@ -51,7 +51,7 @@ def traffic_from_profiles(workload, kernel):
 
 
 def host_cpu():
-    """CPU model and the cores this process may use (the GPU machine's host share)."""
+    """CPU model and the cores this process may use (its affinity mask)."""
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -195,7 +195,7 @@ def learned_vs_uniform(dev, trials):
     g = api.Graph(w5.nl, w5.nr, l, r, device=dev)
     del l, r
     B = g.exact()
-    # the judge, timed for context: the exact count and the exact per-vertex counts
+    # the exact answers, timed for context: the exact count and the exact per-vertex counts
     tot = torch.zeros(1, dtype=torch.int64, device=dev)
     e0, e1 = events()
     e0.record(stream)
