@@ -56,16 +56,21 @@ __device__ inline f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
 // d_u^2, log1p max d_u, log1p sum (d_u - 1) (paths v-u-w, w != v), log1p
 // C(d_v, 2), log1p(sum d_u / d_v); each log term scaled by 1/8.  Rows by
 // global id (L ids, then n_left + R id), BF16.
+// A group of NFEAT lanes per vertex (most vertices have few neighbours, so
+// a wave per vertex left most lanes idle): the group sums its neighbours'
+// degrees, reduces over its lanes, and lane i writes feature i.  The sums
+// are integers below 2^53, exact in binary64 in any order.
+constexpr uint32_t FGROUP = NFEAT;
 __global__ __launch_bounds__(256) void k_features(const uint32_t *offS, const uint32_t *adjS,
                                                   const uint32_t *offT, const uint32_t *idS,
                                                   uint32_t nS, uint32_t row0, float side,
                                                   uint16_t *feat) {
-    const uint32_t lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
-    for (uint32_t v = blockIdx.x * wpb + threadIdx.x / WAVE; v < nS; v += gridDim.x * wpb) {
+    const uint32_t lane = threadIdx.x & (FGROUP - 1), gpb = blockDim.x / FGROUP;
+    for (uint32_t v = blockIdx.x * gpb + threadIdx.x / FGROUP; v < nS; v += gridDim.x * gpb) {
         const uint32_t b = offS[v], e = offS[v + 1];
         double s1 = 0, s2 = 0, s3 = 0;
         uint32_t mx = 0;
-        for (uint32_t k = b + lane; k < e; k += WAVE) {
+        for (uint32_t k = b + lane; k < e; k += FGROUP) {
             const uint32_t u = adjS[k];
             const double d = (double)(offT[u + 1] - offT[u]);
             s1 += d;
@@ -73,14 +78,15 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t *offS, const ui
             s3 += d - 1.0;
             mx = max(mx, (uint32_t)d);
         }
+        // partners lane ^ o (o < FGROUP) are in the same group
 #pragma unroll
-        for (int o = WAVE / 2; o > 0; o >>= 1) {
+        for (int o = FGROUP / 2; o > 0; o >>= 1) {
             s1 += __shfl_xor(s1, o, WAVE);
             s2 += __shfl_xor(s2, o, WAVE);
             s3 += __shfl_xor(s3, o, WAVE);
             mx = max(mx, (uint32_t)__shfl_xor(mx, o, WAVE));
         }
-        if (lane < NFEAT) {
+        {
             const double dv = (double)(e - b);
             double x;
             switch (lane) {
@@ -506,7 +512,7 @@ int bfc_mlp_param_count(void) { return P_N; }
 
 int bfc_features(const bfc_graph *g, uint16_t *d_feat, hipStream_t s) {
     if (!g || !d_feat) return BFC_E_NULL;
-    unsigned gl = grid_for(g->n_left, 4), gr = grid_for(g->n_right, 4);
+    unsigned gl = grid_for(g->n_left, 256 / FGROUP), gr = grid_for(g->n_right, 256 / FGROUP);
     if (gl > 8192) gl = 8192;
     if (gr > 8192) gr = 8192;
     if (g->n_left)
